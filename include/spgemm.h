@@ -1,0 +1,199 @@
+/*
+ * spgemm.h -- C ABI of the MI355X (gfx950) local SpGEMM library.
+ *
+ * The library computes the per-GPU hot path of a distributed sparse matrix
+ * product: the local block product C = A B of CSR matrices (paper §2,
+ * problem statement), the accumulation of several block products into one C
+ * over the rounds of the outer algorithm (§3.3.1, Alg. 1 and Eq. (1)/(2)),
+ * the sparse sum of partial products (§4.4), one Markov-clustering
+ * iteration (§5.7), and the gradient of a product at fixed sparsity.
+ *
+ * Conventions shared by every call
+ *  - Array arguments inside spg_csr and every buffer argument are DEVICE
+ *    pointers on the device that owns `stream`; scalars, handles and the
+ *    spg_csr structs themselves are host memory.
+ *  - CSR: row_ptr has nrows+1 int32 entries with row_ptr[0] = 0, non-
+ *    decreasing, row_ptr[nrows] = nnz; col_idx has nnz int32 entries in
+ *    [0, ncols) with no repeated column inside a row; vals has nnz entries
+ *    of the call's dtype.  Column order inside a row of A or B may be
+ *    arbitrary; every output row is canonical (columns strictly ascending).
+ *  - The output pattern is structural: an entry that cancels to 0.0 stays
+ *    stored.
+ *  - The caller owns all memory: outputs and the workspace.  The library
+ *    allocates no device memory and frees none of the caller's.  A plan
+ *    holds host metadata and pointers into the caller's workspace and
+ *    C row pointer, which must outlive the plan's use.
+ *  - Work is queued on `stream` (a hipStream_t; NULL = the null stream).
+ *    Calls return once the work is queued, except where a call says it
+ *    synchronises.
+ *  - Every call returns an spg_status; no exception crosses the ABI and the
+ *    library prints nothing.  Asynchronous device faults surface as
+ *    SPG_ERR_HIP from a later call.
+ */
+#ifndef SPGEMM_H_
+#define SPGEMM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPG_OK = 0,
+  SPG_ERR_INVALID = 1,     /* malformed CSR (with validation on) or bad value */
+  SPG_ERR_SHAPE = 2,       /* operand shapes do not line up */
+  SPG_ERR_OVERFLOW = 3,    /* nnz of an output exceeds 2^31-1 */
+  SPG_ERR_CAPACITY = 4,    /* output larger than the capacity given */
+  SPG_ERR_WORKSPACE = 5,   /* workspace missing or too small */
+  SPG_ERR_HIP = 6,         /* a HIP runtime call failed */
+  SPG_ERR_UNSUPPORTED = 7, /* argument combination not supported */
+  SPG_ERR_ARG = 8          /* NULL pointer or out-of-range scalar argument */
+} spg_status;
+
+typedef enum { SPG_F32 = 0, SPG_F64 = 1 } spg_dtype;
+
+typedef struct {
+  int32_t nrows, ncols;
+  int64_t nnz;
+  const int32_t *row_ptr; /* device [nrows+1] */
+  const int32_t *col_idx; /* device [nnz] */
+  const void *vals;       /* device [nnz] of the call's dtype; unused by pattern-only steps */
+} spg_csr;
+
+typedef struct spg_plan_s *spg_plan;
+
+/* Maximum number of block products / merge operands in one call. */
+#define SPG_MAX_PARTS 16
+
+/* Plan flags (spgemm_plan_create). */
+#define SPG_FLAG_VALIDATE 1u  /* check CSR well-formedness on the device (one extra pass) */
+
+/* ------------------------------------------------------------------------
+ * Plans and workspace
+ * --------------------------------------------------------------------- */
+
+/* Create an empty plan.  flags: SPG_FLAG_*.  Host only. */
+int spgemm_plan_create(uint32_t flags, spg_plan *plan_out);
+
+/* Release a plan (host metadata only; no device memory is touched). */
+void spgemm_plan_destroy(spg_plan plan);
+
+/* Bytes of device workspace needed by a product with m output rows, n
+ * output columns and kmax = the largest inner dimension among its blocks
+ * (for a merge pass kmax = m).  Host only; depends on shapes alone, so it
+ * can be sized before any device work (and before a graph capture). */
+int spgemm_workspace_size(int32_t m, int32_t n, int32_t kmax, size_t *bytes);
+
+/* Status word that device kernels raise in capture-safe mode (overflow,
+ * capacity), read back on the host (synchronises the plan's last stream).
+ * *device_status_host receives an spg_status. */
+int spgemm_plan_status(spg_plan plan, int32_t *device_status_host);
+
+/* Last known nnz of the plan's output (after a synchronising symbolic call
+ * or after spgemm_plan_status), and the number of scalar products. */
+int spgemm_plan_info(spg_plan plan, int64_t *nnz, int64_t *products);
+
+const char *spgemm_status_string(int status);
+
+/* ------------------------------------------------------------------------
+ * Product  C = sum_{k<K} A_k B_k   (K = 1: the plain block product, §2;
+ * K > 1: the per-round partial products of §3.3.1 Alg. 1 accumulated into
+ * one C without materialising the partials, the fused form of §4.4's sum).
+ * All A_k share nrows = m, all B_k share ncols = n, A_k.ncols = B_k.nrows.
+ * --------------------------------------------------------------------- */
+
+/* Symbolic pass: per-row products (flop upper bound), row binning, exact
+ * distinct-column count per row and the exclusive scan into C_row_ptr.
+ *   C_row_ptr   device [m+1], written.
+ *   C_nnz_host  non-NULL: the call synchronises `stream` and stores nnz(C)
+ *               (eager mode).  NULL: nothing is read back (capture-safe
+ *               mode); nnz(C) > capacity raises SPG_ERR_CAPACITY in the
+ *               device status word and the numeric pass then writes nothing.
+ *   capacity    capture-safe mode only: entries the caller allocated for C.
+ *   workspace   device, at least spgemm_workspace_size(m, n, max_k k_k).
+ * Errors: SPG_ERR_SHAPE, SPG_ERR_ARG, SPG_ERR_WORKSPACE, SPG_ERR_OVERFLOW
+ * (eager: returned; capture-safe: device status), SPG_ERR_INVALID (with
+ * validation on), SPG_ERR_HIP. */
+int spgemm_symbolic(spg_plan plan, int32_t K, const spg_csr *A, const spg_csr *B,
+                    int32_t *C_row_ptr, int64_t *C_nnz_host, int64_t capacity,
+                    void *workspace, size_t ws_bytes, void *stream);
+
+/* Numeric pass: values and canonical column order of C, for the same K
+ * operand patterns as the plan's symbolic call (values may differ: the plan
+ * is reusable at fixed sparsity).
+ *   C_col_idx  device [nnz(C)] int32, written.
+ *   C_vals     device [nnz(C)] of dtype, written.
+ * Accumulation is in dtype (FP32 or FP64). */
+int spgemm_numeric(spg_plan plan, int32_t K, const spg_csr *A, const spg_csr *B,
+                   spg_dtype dtype, int32_t *C_col_idx, void *C_vals, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Sparse sum  C = sum_{k<K} P_k  of same-shape matrices (§4.4: the partial
+ * products of the rounds summed into one C; union of patterns, values
+ * added).  The P_k need not be canonical.  Two phases share the plan:
+ * first call with C_col_idx == NULL and C_vals == NULL to build C_row_ptr
+ * (and nnz, as in spgemm_symbolic), then call again with the output
+ * buffers to fill them.
+ * --------------------------------------------------------------------- */
+int spgemm_merge(spg_plan plan, int32_t K, const spg_csr *P, spg_dtype dtype,
+                 int32_t *C_row_ptr, int64_t *C_nnz_host, int64_t capacity,
+                 int32_t *C_col_idx, void *C_vals, void *workspace, size_t ws_bytes,
+                 void *stream);
+
+/* ------------------------------------------------------------------------
+ * Backward at fixed sparsity of C = A B (K = 1) for a loss L with
+ * dL/dC = dC on S(C):
+ *   dA = (dC B^T) restricted to S(A),  dB = (A^T dC) restricted to S(B).
+ *   dC         CSR with the pattern the plan's numeric pass produced; its
+ *              vals are dL/dC_ij.
+ *   dA_vals    device [nnz(A)] or NULL (not computed), written.
+ *   dB_vals    device [nnz(B)] or NULL, written (zeroed first, then
+ *              accumulated with device atomics: the summation order of a
+ *              dB entry is not fixed).
+ * Not in the paper; the definition is the derivative of the bilinear map
+ * (A, B) -> A B at a fixed pattern. */
+int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg_csr *dC,
+                    spg_dtype dtype, void *dA_vals, void *dB_vals, void *stream);
+
+/* ------------------------------------------------------------------------
+ * One Markov-clustering iteration (§5.7) on X = M^T (row c of X is
+ * column c of M, so (M M)^T = X X):
+ *   E = X X; e <- e^r; divide each row by its sum; drop e < prune;
+ *   keep the topk largest (ties to the smaller column); an emptied row
+ *   keeps its largest entry; divide each row by its new sum.
+ * The unpruned product is never stored.
+ *   Y_row_ptr  device [n+1], written.
+ *   Y_col_idx, Y_vals  device, capacity entries each (capacity >= the
+ *              output nnz; n*min(topk,n) always suffices), written.
+ *   Y_nnz_host non-NULL: synchronises and returns nnz(Y); NULL: capture-
+ *              safe (overflow of capacity -> SPG_ERR_CAPACITY in the device
+ *              status word).
+ *   workspace  device, at least spgemm_mcl_workspace_size(n, topk).
+ * FP32 only (dtype SPG_F32); inflation exponent r in 1..8. */
+int spgemm_mcl_workspace_size(int32_t n, int32_t topk, size_t *bytes);
+int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune,
+                         int32_t topk, int32_t *Y_row_ptr, int32_t *Y_col_idx,
+                         float *Y_vals, int64_t capacity, int64_t *Y_nnz_host,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Tuning (chosen by the autotuner outside any graph capture).
+ * --------------------------------------------------------------------- */
+#define SPG_NBINS 16
+
+typedef struct {
+  int32_t lanes[SPG_NBINS];     /* threads cooperating on one row, per bin (power of 2) */
+  int32_t sub;                  /* lanes reading one B row together (4..64, power of 2) */
+  int32_t heavy_slots;          /* concurrent heavy rows (0 = from the workspace size) */
+  int32_t max_window;           /* largest probe displacement ranked in place */
+} spg_tuning;
+
+int spgemm_default_tuning(spg_tuning *t);
+int spgemm_plan_set_tuning(spg_plan plan, const spg_tuning *t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPGEMM_H_ */

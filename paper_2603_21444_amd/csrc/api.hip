@@ -1,0 +1,458 @@
+// C ABI of the local SpGEMM library (declared in include/spgemm.h).
+//
+// Host code only: argument checks, workspace layout, plan bookkeeping and
+// the launch sequence of each call.  All arithmetic runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace spg;
+
+struct spg_plan_s {
+  uint32_t flags = 0;
+  spg_tuning tun{};
+  bool tun_set = false;
+  // state of the last symbolic (or merge count) call
+  bool sym_done = false;
+  bool merge_mode = false;
+  bool counts_known = false;
+  int K = 0, m = 0, n = 0;
+  int kdim[SPG_MAX_PARTS] = {0};
+  int64_t annz[SPG_MAX_PARTS] = {0}, bnnz[SPG_MAX_PARTS] = {0};
+  int num_count[kNB] = {0};
+  int64_t nnz = -1, products = -1;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  WsLayout L{};
+  int32_t *crp = nullptr;
+  hipStream_t stream = nullptr;
+  WsHeader *host_hdr = nullptr;  // pinned readback buffer
+};
+
+namespace spg {
+
+static std::mutex g_dev_mu;
+static std::vector<DevInfo> g_dev;
+
+static int maxbin_for(size_t lds, size_t slot_bytes, size_t extra) {
+  int b = kMaxLdsBin;
+  while (b > 1 && (size_t)(bin_slots(b) + kTail) * slot_bytes + extra > lds) --b;
+  return b;
+}
+
+const DevInfo &dev_info() {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(g_dev_mu);
+  for (const DevInfo &d : g_dev)
+    if (d.device == dev) return d;
+  DevInfo d;
+  d.device = dev;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+    d.cus = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+      v > 0)
+    d.lds_per_block = (size_t)v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess &&
+      v > 0)
+    d.lds_per_cu = (size_t)v;
+  if (d.lds_per_cu < d.lds_per_block) d.lds_per_cu = d.lds_per_block;
+  // the largest table of each pass that fits one block's LDS
+  d.sym_maxbin = maxbin_for(d.lds_per_block, 4, 64);
+  d.num_maxbin_f32 = maxbin_for(d.lds_per_block, 8, 128);
+  d.num_maxbin_f64 = maxbin_for(d.lds_per_block, 12, 128);
+  (void)configure_lds_limits(d.lds_per_block);
+  (void)hipGetLastError();
+  g_dev.push_back(d);
+  return g_dev.back();
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int default_heavy_slots(int64_t n) {
+  const int64_t budget = (int64_t)2 << 30;  // dense accumulators of concurrent heavy rows
+  int64_t s = budget / (std::max<int64_t>(n, 1) * 8);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(256, s));
+}
+
+WsLayout ws_layout(int64_t m, int64_t n, int heavy_slots) {
+  WsLayout L{};
+  const int64_t nblk = m == 0 ? 1 : (m + 255) / 256;
+  const int64_t nparts = m == 0 ? 1 : (m + 2047) / 2048;
+  size_t o = 0;
+  o = align256(sizeof(WsHeader));
+  L.problem = o;
+  o = align256(o + sizeof(Problem));
+  o = std::max<size_t>(o, 4096);
+  L.binid = o;
+  o = align256(o + (size_t)std::max<int64_t>(m, 1));
+  L.rows = o;
+  o = align256(o + 4 * (size_t)std::max<int64_t>(m, 1));
+  L.fbrows = o;
+  o = align256(o + 4 * (size_t)std::max<int64_t>(m, 1));
+  L.blockhist = o;
+  o = align256(o + 4 * (size_t)(nblk * kNB));
+  L.scanpart = o;
+  o = align256(o + 8 * (size_t)nparts);
+  L.heavy_slots = heavy_slots;
+  L.heavyacc = o;
+  o = align256(o + (size_t)heavy_slots * (size_t)std::max<int64_t>(n, 1) * 8);
+  L.heavymap = o;  // used when a heavy row's bitmap does not fit in LDS
+  o = align256(o + (size_t)heavy_slots * (size_t)((std::max<int64_t>(n, 1) + 31) / 32) * 4);
+  L.total = o;
+  return L;
+}
+
+}  // namespace spg
+
+namespace {
+
+spg_tuning default_tuning() {
+  spg_tuning t{};
+  // lanes per row for bins of at most 16, 32, ..., 16384 products or entries
+  const int lanes[kNB] = {0, 8, 16, 16, 32, 64, 128, 256, 256, 512, 1024, 1024, 1024, 1024, 1024, 1024};
+  for (int b = 0; b < kNB; ++b) t.lanes[b] = lanes[b];
+  t.sub = 16;
+  t.heavy_slots = 0;
+  t.max_window = 32;
+  return t;
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_tuning(const spg_tuning &t) {
+  for (int b = 1; b < kNB; ++b)
+    if (!pow2(t.lanes[b]) || t.lanes[b] > 1024) return SPG_ERR_ARG;
+  if (!pow2(t.sub) || t.sub < 1 || t.sub > 64) return SPG_ERR_ARG;
+  if (t.heavy_slots < 0 || t.max_window < 1) return SPG_ERR_ARG;
+  return SPG_OK;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SPG_OK : SPG_ERR_HIP; }
+
+int read_header(spg_plan p, hipStream_t st) {
+  if (!p->host_hdr) {
+    if (hipHostMalloc(reinterpret_cast<void **>(&p->host_hdr), sizeof(WsHeader)) != hipSuccess) {
+      p->host_hdr = nullptr;
+      return SPG_ERR_HIP;
+    }
+  }
+  if (hipMemcpyAsync(p->host_hdr, p->ws, sizeof(WsHeader), hipMemcpyDeviceToHost, st) !=
+      hipSuccess)
+    return SPG_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return SPG_ERR_HIP;
+  return SPG_OK;
+}
+
+int status_from_bits(int bits) {
+  if (bits & kStatInvalid) return SPG_ERR_INVALID;
+  if (bits & kStatOverflow) return SPG_ERR_OVERFLOW;
+  if (bits & kStatCapacity) return SPG_ERR_CAPACITY;
+  return SPG_OK;
+}
+
+BinPlan make_binplan(spg_plan p, int maxbin, bool counts_known, const int *counts) {
+  BinPlan bp;
+  bp.known = counts_known;
+  if (counts_known)
+    for (int b = 0; b < kNB; ++b) bp.count[b] = counts[b];
+  for (int b = 0; b < kNB; ++b) bp.lanes[b] = p->tun.lanes[b];
+  bp.sub = p->tun.sub;
+  bp.maxbin = maxbin;
+  bp.heavy_slots = p->L.heavy_slots;
+  bp.n = p->n;
+  bp.maxwin = p->tun.max_window;
+  return bp;
+}
+
+// Shared symbolic sequence for products (identity == false) and merges.
+int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr *B,
+                 int32_t *C_row_ptr, int64_t *C_nnz_host, int64_t capacity, void *workspace,
+                 size_t ws_bytes, hipStream_t st) {
+  const int m = pr.m, n = pr.n;
+  const int heavy = p->tun.heavy_slots > 0 ? p->tun.heavy_slots : default_heavy_slots(n);
+  const WsLayout L = ws_layout(m, n, heavy);
+  if (!workspace || ws_bytes < L.total) return SPG_ERR_WORKSPACE;
+  if (!C_nnz_host && capacity < 0) return SPG_ERR_ARG;
+  p->sym_done = false;
+  p->counts_known = false;
+  p->ws = static_cast<char *>(workspace);
+  p->ws_bytes = ws_bytes;
+  p->L = L;
+  p->crp = C_row_ptr;
+  p->stream = st;
+  p->K = pr.K;
+  p->m = m;
+  p->n = n;
+  p->nnz = -1;
+  p->products = -1;
+  const DevInfo &D = dev_info();
+  char *ws = p->ws;
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  Problem *dpr = reinterpret_cast<Problem *>(ws + L.problem);
+  hipError_t e = launch_setup(pr, dpr, hdr, true, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  const bool eager = C_nnz_host != nullptr;
+  if (p->flags & SPG_FLAG_VALIDATE) {
+    // every later kernel exits once the status word is raised, so invalid
+    // operands are never dereferenced; eagerly the call returns right here
+    for (int k = 0; k < pr.K; ++k) {
+      if (A) launch_validate(A[k].row_ptr, A[k].col_idx, A[k].nrows, A[k].ncols, A[k].nnz, hdr, st);
+      launch_validate(B[k].row_ptr, B[k].col_idx, B[k].nrows, B[k].ncols, B[k].nnz, hdr, st);
+    }
+    if (eager) {
+      int rc = read_header(p, st);
+      if (rc) return rc;
+      rc = status_from_bits(p->host_hdr->status);
+      if (rc) return rc;
+    }
+  }
+  // a1 + a2: products per row and bins by products
+  e = launch_binning(dpr, nullptr, 0, m, D.sym_maxbin, L, ws, C_row_ptr, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  BinPlan sbp;
+  if (eager) {
+    int rc = read_header(p, st);
+    if (rc) return rc;
+    rc = status_from_bits(p->host_hdr->status);
+    if (rc) return rc;
+    sbp = make_binplan(p, D.sym_maxbin, true, p->host_hdr->bin_count);
+  } else {
+    sbp = make_binplan(p, D.sym_maxbin, false, nullptr);
+  }
+  // a3: exact row counts, then the scan into row_ptr
+  e = launch_symbolic_bins(dpr, sbp, L, ws, C_row_ptr, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  e = launch_scan(C_row_ptr, m, eager ? -1 : capacity, L, ws, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  // numeric bins by exact row nnz
+  e = launch_binning(dpr, C_row_ptr, 1, m, D.num_maxbin_f32, L, ws, nullptr, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  if (eager) {
+    int rc = read_header(p, st);
+    if (rc) return rc;
+    rc = status_from_bits(p->host_hdr->status);
+    if (rc) return rc;
+    p->nnz = p->host_hdr->nnz_total;
+    p->products = p->host_hdr->products_total;
+    for (int b = 0; b < kNB; ++b) p->num_count[b] = p->host_hdr->bin_count[b];
+    p->counts_known = true;
+    *C_nnz_host = p->nnz;
+  }
+  p->sym_done = true;
+  return SPG_OK;
+}
+
+int fill_parts(Problem &pr, int K, const spg_csr *A, const spg_csr *B, bool identity) {
+  if (K < 1 || K > SPG_MAX_PARTS) return SPG_ERR_ARG;
+  if (!B || (!identity && !A)) return SPG_ERR_ARG;
+  std::memset(&pr, 0, sizeof(pr));
+  pr.K = K;
+  pr.m = identity ? B[0].nrows : A[0].nrows;
+  pr.n = B[0].ncols;
+  if (pr.m < 0 || pr.n < 0) return SPG_ERR_SHAPE;
+  for (int k = 0; k < K; ++k) {
+    Part &P = pr.part[k];
+    if (identity) {
+      if (B[k].nrows != pr.m || B[k].ncols != pr.n) return SPG_ERR_SHAPE;
+      P.a_identity = 1;
+      P.kdim = pr.m;
+    } else {
+      if (A[k].nrows != pr.m || B[k].ncols != pr.n || A[k].ncols != B[k].nrows)
+        return SPG_ERR_SHAPE;
+      if (A[k].nnz < 0 || A[k].nnz > 0x7fffffffLL) return SPG_ERR_ARG;
+      if (!A[k].row_ptr || (A[k].nnz > 0 && !A[k].col_idx)) return SPG_ERR_ARG;
+      P.arp = A[k].row_ptr;
+      P.acol = A[k].col_idx;
+      P.aval = A[k].vals;
+      P.kdim = A[k].ncols;
+    }
+    if (B[k].nnz < 0 || B[k].nnz > 0x7fffffffLL) return SPG_ERR_ARG;
+    if (!B[k].row_ptr || (B[k].nnz > 0 && !B[k].col_idx)) return SPG_ERR_ARG;
+    P.brp = B[k].row_ptr;
+    P.bcol = B[k].col_idx;
+    P.bval = B[k].vals;
+  }
+  return SPG_OK;
+}
+
+int check_values(int K, const spg_csr *A, const spg_csr *B, bool identity) {
+  for (int k = 0; k < K; ++k) {
+    if (!identity && A[k].nnz > 0 && !A[k].vals) return SPG_ERR_ARG;
+    if (B[k].nnz > 0 && !B[k].vals) return SPG_ERR_ARG;
+  }
+  return SPG_OK;
+}
+
+void remember_operands(spg_plan p, int K, const spg_csr *A, const spg_csr *B) {
+  for (int k = 0; k < K; ++k) {
+    p->kdim[k] = A ? A[k].ncols : p->m;
+    p->annz[k] = A ? A[k].nnz : -1;
+    p->bnnz[k] = B[k].nnz;
+  }
+}
+
+bool same_operands(spg_plan p, int K, const spg_csr *A, const spg_csr *B) {
+  if (K != p->K) return false;
+  for (int k = 0; k < K; ++k) {
+    if ((A ? A[k].ncols : p->m) != p->kdim[k]) return false;
+    if ((A ? A[k].nnz : -1) != p->annz[k] || B[k].nnz != p->bnnz[k]) return false;
+    if (B[k].ncols != p->n || (A ? A[k].nrows : B[k].nrows) != p->m) return false;
+  }
+  return true;
+}
+
+int run_numeric(spg_plan p, const Problem &pr, spg_dtype dtype, int32_t *C_col_idx,
+                void *C_vals, hipStream_t st) {
+  if (dtype != SPG_F32 && dtype != SPG_F64) return SPG_ERR_ARG;
+  if (p->counts_known && p->nnz > 0 && (!C_col_idx || !C_vals)) return SPG_ERR_ARG;
+  const DevInfo &D = dev_info();
+  char *ws = p->ws;
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  Problem *dpr = reinterpret_cast<Problem *>(ws + p->L.problem);
+  hipError_t e = launch_setup(pr, dpr, hdr, false, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  const int maxbin = dtype == SPG_F64 ? D.num_maxbin_f64 : D.num_maxbin_f32;
+  BinPlan bp = make_binplan(p, maxbin, p->counts_known, p->num_count);
+  e = launch_numeric(dpr, bp, p->L, ws, p->crp, C_col_idx, C_vals, (int)dtype, st);
+  p->stream = st;
+  return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int spgemm_plan_create(uint32_t flags, spg_plan *plan_out) {
+  if (!plan_out) return SPG_ERR_ARG;
+  *plan_out = nullptr;
+  spg_plan p = new (std::nothrow) spg_plan_s();
+  if (!p) return SPG_ERR_ARG;
+  p->flags = flags;
+  p->tun = default_tuning();
+  *plan_out = p;
+  return SPG_OK;
+}
+
+void spgemm_plan_destroy(spg_plan plan) {
+  if (!plan) return;
+  if (plan->host_hdr) (void)hipHostFree(plan->host_hdr);
+  delete plan;
+}
+
+int spgemm_workspace_size(int32_t m, int32_t n, int32_t kmax, size_t *bytes) {
+  if (!bytes || m < 0 || n < 0 || kmax < 0) return SPG_ERR_ARG;
+  *bytes = ws_layout(m, n, default_heavy_slots(n)).total;
+  return SPG_OK;
+}
+
+int spgemm_plan_status(spg_plan plan, int32_t *device_status_host) {
+  if (!plan || !device_status_host) return SPG_ERR_ARG;
+  if (!plan->ws) {
+    *device_status_host = SPG_OK;
+    return SPG_OK;
+  }
+  int rc = read_header(plan, plan->stream);
+  if (rc) return rc;
+  *device_status_host = status_from_bits(plan->host_hdr->status);
+  plan->nnz = plan->host_hdr->nnz_total;
+  plan->products = plan->host_hdr->products_total;
+  return SPG_OK;
+}
+
+int spgemm_plan_info(spg_plan plan, int64_t *nnz, int64_t *products) {
+  if (!plan) return SPG_ERR_ARG;
+  if (nnz) *nnz = plan->nnz;
+  if (products) *products = plan->products;
+  return SPG_OK;
+}
+
+const char *spgemm_status_string(int status) {
+  switch (status) {
+    case SPG_OK: return "ok";
+    case SPG_ERR_INVALID: return "invalid CSR input";
+    case SPG_ERR_SHAPE: return "operand shapes do not match";
+    case SPG_ERR_OVERFLOW: return "output nnz exceeds 2^31-1";
+    case SPG_ERR_CAPACITY: return "output larger than the given capacity";
+    case SPG_ERR_WORKSPACE: return "workspace missing or too small";
+    case SPG_ERR_HIP: return "HIP runtime error";
+    case SPG_ERR_UNSUPPORTED: return "unsupported argument combination";
+    case SPG_ERR_ARG: return "bad argument";
+    default: return "unknown status";
+  }
+}
+
+int spgemm_default_tuning(spg_tuning *t) {
+  if (!t) return SPG_ERR_ARG;
+  *t = default_tuning();
+  return SPG_OK;
+}
+
+int spgemm_plan_set_tuning(spg_plan plan, const spg_tuning *t) {
+  if (!plan || !t) return SPG_ERR_ARG;
+  int rc = check_tuning(*t);
+  if (rc) return rc;
+  plan->tun = *t;
+  plan->tun_set = true;
+  return SPG_OK;
+}
+
+int spgemm_symbolic(spg_plan plan, int32_t K, const spg_csr *A, const spg_csr *B,
+                    int32_t *C_row_ptr, int64_t *C_nnz_host, int64_t capacity, void *workspace,
+                    size_t ws_bytes, void *stream) {
+  if (!plan || !C_row_ptr) return SPG_ERR_ARG;
+  Problem pr;
+  int rc = fill_parts(pr, K, A, B, false);
+  if (rc) return rc;
+  plan->merge_mode = false;
+  rc = run_symbolic(plan, pr, A, B, C_row_ptr, C_nnz_host, capacity, workspace, ws_bytes,
+                    static_cast<hipStream_t>(stream));
+  if (rc == SPG_OK) remember_operands(plan, K, A, B);
+  return rc;
+}
+
+int spgemm_numeric(spg_plan plan, int32_t K, const spg_csr *A, const spg_csr *B,
+                   spg_dtype dtype, int32_t *C_col_idx, void *C_vals, void *stream) {
+  if (!plan) return SPG_ERR_ARG;
+  if (!plan->sym_done || plan->merge_mode) return SPG_ERR_ARG;
+  Problem pr;
+  int rc = fill_parts(pr, K, A, B, false);
+  if (rc) return rc;
+  if (!same_operands(plan, K, A, B)) return SPG_ERR_SHAPE;
+  rc = check_values(K, A, B, false);
+  if (rc) return rc;
+  return run_numeric(plan, pr, dtype, C_col_idx, C_vals, static_cast<hipStream_t>(stream));
+}
+
+int spgemm_merge(spg_plan plan, int32_t K, const spg_csr *P, spg_dtype dtype,
+                 int32_t *C_row_ptr, int64_t *C_nnz_host, int64_t capacity, int32_t *C_col_idx,
+                 void *C_vals, void *workspace, size_t ws_bytes, void *stream) {
+  if (!plan) return SPG_ERR_ARG;
+  Problem pr;
+  int rc = fill_parts(pr, K, nullptr, P, true);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!C_col_idx && !C_vals) {
+    if (!C_row_ptr) return SPG_ERR_ARG;
+    plan->merge_mode = true;
+    rc = run_symbolic(plan, pr, nullptr, P, C_row_ptr, C_nnz_host, capacity, workspace,
+                      ws_bytes, st);
+    if (rc == SPG_OK) remember_operands(plan, K, nullptr, P);
+    return rc;
+  }
+  if (!plan->sym_done || !plan->merge_mode) return SPG_ERR_ARG;
+  if (!same_operands(plan, K, nullptr, P)) return SPG_ERR_SHAPE;
+  rc = check_values(K, nullptr, P, true);
+  if (rc) return rc;
+  return run_numeric(plan, pr, dtype, C_col_idx, C_vals, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Device-side definitions shared by the SpGEMM kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/spgemm.h"
+
+namespace spg {
+
+constexpr int kWave = 64;
+constexpr int kEmpty = -1;          // empty hash slot (column indices are >= 0)
+constexpr int kNB = SPG_NBINS;      // row bins
+constexpr int kHeavyBin = 12;       // rows beyond every LDS table
+constexpr int kMaxLdsBin = 11;      // largest LDS bin index
+constexpr int kTail = 64;           // extra slots after a table: probes never wrap early
+constexpr int kLdsBitmapCols = 1 << 20;  // columns a heavy row can mark in LDS (128 KiB)
+
+// Status bits raised by kernels in the workspace header.
+constexpr int kStatOverflow = 1;
+constexpr int kStatCapacity = 2;
+constexpr int kStatInvalid = 4;
+
+// Upper edge of bin b (b >= 1): rows whose key (products or nnz) lies in
+// (edge(b-1), edge(b)] land in bin b; bin 0 holds rows with key 0.
+__host__ __device__ inline int64_t bin_edge(int b) { return b <= 0 ? 0 : (int64_t)8 << b; }
+
+__host__ __device__ inline int bin_of(int64_t key, int maxbin) {
+  if (key <= 0) return 0;
+  int b = 1;
+  while (b <= maxbin && key > bin_edge(b)) ++b;
+  return b > maxbin ? kHeavyBin : b;
+}
+
+// Hash table slots of an LDS bin: twice the bin's upper edge (load <= 1/2).
+__host__ __device__ inline int bin_slots(int b) { return (int)(2 * bin_edge(b)); }
+
+// One block product A_k B_k of the batched form, or one merge operand
+// (a_identity: row i of A_k is the single entry (i, 1)).
+struct Part {
+  const int32_t *arp, *acol;
+  const void *aval;
+  const int32_t *brp, *bcol;
+  const void *bval;
+  int32_t a_identity;
+  int32_t kdim;
+};
+
+struct Problem {
+  int32_t K, m, n;
+  Part part[SPG_MAX_PARTS];
+};
+
+// Workspace header (first 4 KiB of the caller's workspace).
+struct WsHeader {
+  int32_t status;
+  int32_t pad0;
+  int64_t nnz_total;
+  int64_t products_total;
+  int32_t bin_count[kNB];
+  int32_t bin_start[kNB + 1];
+  int32_t fallback_count;
+  int32_t heavy_cursor;
+};
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` strictly below this lane.
+__device__ inline int mbcnt(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+// Order-preserving home slot: floor(col * T / n) computed as the high half of
+// col * floor(T * 2^32 / n); `mul` == 0 means T >= n and the slot is col.
+__device__ inline uint32_t mono_slot(uint32_t col, uint32_t mul) {
+  return mul ? __umulhi(col, mul) : col;
+}
+
+__host__ inline uint32_t mono_mul(int64_t T, int64_t n) {
+  if (T >= n) return 0u;
+  return (uint32_t)(((uint64_t)T << 32) / (uint64_t)n);
+}
+
+// Fibonacci hashing for tables that need no order.
+__device__ inline uint32_t scramble_slot(uint32_t col, int log2T) {
+  return (col * 2654435769u) >> (32 - log2T);
+}
+
+template <typename T>
+__device__ inline void lds_add(T *p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <typename T>
+__device__ inline void global_add(T *p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ inline T ld_val(const void *p, int64_t i) {
+  return static_cast<const T *>(p)[i];
+}
+
+// Entries of row i of A_k: [start, end) into acol/aval (identity: one entry).
+__device__ inline void a_row(const Part &P, int i, int &s, int &e) {
+  if (P.a_identity) { s = 0; e = 1; }
+  else { s = P.arp[i]; e = P.arp[i + 1]; }
+}
+
+template <typename VT>
+__device__ inline void a_entry(const Part &P, int i, int p, int &brow, VT &a) {
+  if (P.a_identity) { brow = i; a = VT(1); }
+  else { brow = P.acol[p]; a = ld_val<VT>(P.aval, p); }
+}
+
+__device__ inline int a_entry_row(const Part &P, int i, int p) {
+  return P.a_identity ? i : P.acol[p];
+}
+
+}  // namespace spg

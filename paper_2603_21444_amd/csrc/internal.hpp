@@ -1,0 +1,61 @@
+// Host-side internals shared by the launchers and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace spg {
+
+struct DevInfo {
+  int device = -1;
+  int cus = 256;
+  size_t lds_per_block = 65536;
+  size_t lds_per_cu = 163840;
+  int sym_maxbin = kMaxLdsBin;   // largest LDS bin of the symbolic pass
+  int num_maxbin_f32 = 10;       // largest LDS bin of the FP32 numeric pass
+  int num_maxbin_f64 = 9;        // largest LDS bin of the FP64 numeric pass
+};
+
+const DevInfo &dev_info();
+
+// Byte offsets of the workspace regions.
+struct WsLayout {
+  size_t problem, binid, rows, fbrows, blockhist, scanpart, heavyacc, heavymap, total;
+  int heavy_slots;
+};
+
+WsLayout ws_layout(int64_t m, int64_t n, int heavy_slots);
+int default_heavy_slots(int64_t n);
+
+// What a pass needs to know about the bins: counts when read back (eager),
+// lanes per row per bin, B-row sub-group width.
+struct BinPlan {
+  bool known = false;
+  int count[kNB] = {0};
+  int lanes[kNB] = {0};
+  int sub = 16;
+  int maxbin = kMaxLdsBin;  // last LDS bin; bins above go to the heavy kernel
+  int heavy_slots = 1;
+  int n = 0;
+  int maxwin = 32;
+};
+
+hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool reset,
+                        hipStream_t st);
+hipError_t launch_validate(const int32_t *rp, const int32_t *col, int rows, int ncols,
+                           int64_t nnz, WsHeader *hdr, hipStream_t st);
+hipError_t launch_binning(const Problem *dpr, const int32_t *crp, int mode, int m, int maxbin,
+                          const WsLayout &L, char *ws, int32_t *cnt_zero, hipStream_t st);
+hipError_t launch_scan(int32_t *rp, int m, int64_t capacity, const WsLayout &L, char *ws,
+                       hipStream_t st);
+hipError_t launch_symbolic_bins(const Problem *dpr, const BinPlan &bp, const WsLayout &L,
+                                char *ws, int32_t *cnt, hipStream_t st);
+hipError_t launch_numeric(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
+                          const int32_t *crp, int32_t *ccol, void *cval, int dtype,
+                          hipStream_t st);
+hipError_t configure_lds_limits(size_t lds_max);
+
+}  // namespace spg

@@ -47,3 +47,34 @@ def assert_canonical(M):
         assert M.indices.min() >= 0 and M.indices.max() < M.shape[1]
         same = rid[1:] == rid[:-1]
         assert np.all(M.indices[1:][same] > M.indices[:-1][same])
+
+
+def row_subset(M, rows) -> HostCSR:
+    """Rows `rows` of M (in that order) as a new CSR with the same columns."""
+    rows = np.asarray(rows, dtype=np.int64)
+    lens = (M.indptr[rows + 1] - M.indptr[rows]).astype(np.int64)
+    ip = np.zeros(rows.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=ip[1:])
+    idx = np.concatenate([np.arange(M.indptr[r], M.indptr[r + 1]) for r in rows]) if rows.size else np.zeros(0, np.int64)
+    return HostCSR((rows.size, M.shape[1]), ip, M.indices[idx].astype(np.int32),
+                   None if M.data is None else M.data[idx])
+
+
+def tol_for(dtype) -> float:
+    """Value tolerance relative to S_ij = sum_k |a_ik||b_kj| against the FP64
+    oracle: 1e-12 for FP64, 1e-5 for FP32 accumulation."""
+    return 1e-12 if np.dtype(dtype) == np.float64 else 1e-5
+
+
+def assert_same_csr(got, ref, S, dtype, exact=False, what=""):
+    """Bit-exact row_ptr and col_idx; values exact or within tol*S."""
+    assert tuple(got.shape) == tuple(ref.shape), what
+    assert np.array_equal(np.asarray(got.indptr, np.int64), np.asarray(ref.indptr, np.int64)), f"{what}: row_ptr differs"
+    assert np.array_equal(got.indices, ref.indices), f"{what}: col_idx differs"
+    g = np.asarray(got.data, dtype=np.float64)
+    if exact:
+        assert np.array_equal(g, ref.data), f"{what}: values differ"
+    else:
+        err = np.abs(g - ref.data)
+        bad = err > tol_for(dtype) * S
+        assert not bad.any(), f"{what}: {int(bad.sum())} values out of tolerance, worst {float((err / np.maximum(S, 1e-300)).max()):.3e}"

@@ -1,0 +1,244 @@
+"""GPU parity of the product C = A B (symbolic + numeric) against the FP64
+oracle: bit-exact row_ptr and col_idx, values within tolerance (or exact
+for small-integer values).  Calls go through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_21444_amd import synth
+from helpers import assert_same_csr, row_subset
+
+pytestmark = pytest.mark.gpu
+
+SEED = 20260321
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    from paper_2603_21444_amd import binding
+    assert torch.cuda.is_available()
+    binding.lib()
+    return binding
+
+
+def gpu_product(binding, A, Bm, dtype):
+    dA = binding.to_device(A, dtype=dtype)
+    dB = binding.to_device(Bm, dtype=dtype)
+    C = binding.spgemm(dA, dB)
+    return C.to_host()
+
+
+def check(binding, A, Bm, dtype, exact=False, what=""):
+    got = gpu_product(binding, A, Bm, dtype)
+    Af = A.with_data(A.data.astype(dtype).astype(np.float64))
+    Bf = Bm.with_data(Bm.data.astype(dtype).astype(np.float64))
+    ref, S = oracle.spgemm(Af, Bf, with_abs=True)
+    assert_same_csr(got, ref, S, dtype, exact, what)
+    return got
+
+
+def test_square_4096_fp64(B):
+    """C = A A, n = 4096, exactly 8 uniform distinct columns per row, FP64 in (0,1]."""
+    A = synth.uniform_csr(4096, 4096, 8, SEED, np.float64, "u01")
+    check(B, A, A, np.float64, what="A*A n=4096")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_small_integers_exact(B, dtype):
+    A = synth.uniform_csr(3000, 2500, 12, 3, dtype, "int", stream=0)
+    Bm = synth.uniform_csr(2500, 2700, 12, 3, dtype, "int", stream=1)
+    got = check(B, A, Bm, dtype, exact=True, what="integers")
+    assert np.sum(got.data == 0) > 0  # cancellations stay stored
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_ragged_rows_span_all_lds_bins(B, dtype):
+    """Row lengths 0..200 times 0..64 give 0..~8000 products per row, so every
+    LDS bin and the empty bin are hit, with ragged tails everywhere."""
+    A = synth.varnnz_csr(6000, 4000, 0, 200, 5, dtype, "normal", stream=0)
+    Bm = synth.varnnz_csr(4000, 30000, 0, 64, 5, dtype, "normal", stream=1)
+    check(B, A, Bm, dtype, what="ragged")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_heavy_rows_lds_bitmap(B, dtype):
+    """A few dense A rows push rows past every LDS table into the heavy path."""
+    n = 60000
+    A = synth.varnnz_csr(300, 5000, 1, 40, 7, dtype, "normal", stream=0)
+    dense_rows = synth.uniform_csr(4, 5000, 2500, 7, dtype, "normal", stream=2)
+    A = _replace_rows(A, [3, 77, 150, 299], dense_rows)
+    Bm = synth.varnnz_csr(5000, n, 4, 32, 7, dtype, "normal", stream=1)
+    check(B, A, Bm, dtype, what="heavy")
+
+
+def test_heavy_rows_global_bitmap(B):
+    """More than 2^20 output columns: heavy rows use the global bitmap."""
+    n = (1 << 20) + 4097
+    A = synth.varnnz_csr(64, 3000, 1, 30, 9, np.float32, "normal", stream=0)
+    dense_rows = synth.uniform_csr(2, 3000, 1500, 9, np.float32, "normal", stream=2)
+    A = _replace_rows(A, [5, 40], dense_rows)
+    Bm = synth.varnnz_csr(3000, n, 8, 24, 9, np.float32, "normal", stream=1)
+    check(B, A, Bm, np.float32, what="heavy, wide")
+
+
+def _replace_rows(A, rows, R):
+    """A with rows `rows` replaced by the rows of R (same column count)."""
+    rows = list(rows)
+    out_rows = []
+    for i in range(A.shape[0]):
+        if i in rows:
+            c, v = R.row(rows.index(i))
+        else:
+            c, v = A.row(i)
+        out_rows.append((c, v))
+    ip = np.zeros(A.shape[0] + 1, dtype=np.int64)
+    np.cumsum([len(c) for c, _ in out_rows], out=ip[1:])
+    return synth.HostCSR(A.shape, ip, np.concatenate([c for c, _ in out_rows]).astype(np.int32),
+                         np.concatenate([v for _, v in out_rows]))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_clustered_columns_take_the_sort_fallback(B, dtype):
+    """Banded B rows give long runs of adjacent output columns: rows whose
+    runs exceed the in-place rank window go through the sort fallback."""
+    k, n = 3000, 3000
+    rows = np.repeat(np.arange(k), 48)
+    cols = (rows + np.tile(np.arange(48), k)) % n
+    ip = np.arange(k + 1, dtype=np.int64) * 48
+    order = np.lexsort((cols, rows))
+    vals = synth.draw_values(synth.rng_for(11), cols.size, "normal", dtype)
+    Bm = synth.HostCSR((k, n), ip, cols[order].astype(np.int32), vals)
+    A = synth.varnnz_csr(2000, k, 1, 40, 11, dtype, "normal")
+    check(B, A, Bm, dtype, what="banded")
+
+
+def test_unsorted_input_rows(B):
+    A = synth.shuffle_rows(synth.uniform_csr(2000, 3000, 20, 13, np.float64, "int", stream=0), 1)
+    Bm = synth.shuffle_rows(synth.uniform_csr(3000, 2000, 20, 13, np.float64, "int", stream=1), 2)
+    check(B, A, Bm, np.float64, exact=True, what="unsorted inputs")
+
+
+def test_identity_and_permutation(B):
+    Bm = synth.varnnz_csr(5000, 7000, 0, 50, 17, np.float32, "normal")
+    got = gpu_product(B, synth.identity_csr(5000, np.float32), Bm, np.float32)
+    assert np.array_equal(got.indptr, Bm.indptr)
+    assert np.array_equal(got.indices, Bm.indices)
+    assert np.array_equal(got.data, Bm.data)
+    P = synth.permutation_csr(5000, 3, np.float32)
+    got = gpu_product(B, P, Bm, np.float32)
+    ref = oracle.spgemm(P, Bm)
+    assert np.array_equal(got.indices, ref.indices)
+    assert np.array_equal(got.data.astype(np.float64), ref.data)
+
+
+def test_degenerate_shapes(B):
+    # no rows
+    A = synth.uniform_csr(0, 10, 0, 1, np.float32)
+    Bm = synth.uniform_csr(10, 10, 3, 1, np.float32)
+    got = gpu_product(B, A, Bm, np.float32)
+    assert got.indptr.tolist() == [0] and got.nnz == 0
+    # all rows empty
+    A = synth.uniform_csr(100, 10, 0, 1, np.float32)
+    got = gpu_product(B, A, Bm, np.float32)
+    assert got.indptr.tolist() == [0] * 101
+    # a single output column: every product lands on column 0
+    A = synth.uniform_csr(1000, 500, 50, 2, np.float64, "int")
+    Bm = synth.HostCSR((500, 1), np.arange(501, dtype=np.int64), np.zeros(500, np.int32),
+                       synth.draw_values(synth.rng_for(2, 3), 500, "int", np.float64))
+    check(B, A, Bm, np.float64, exact=True, what="n=1")
+    # one row, one column inner dimension
+    A = synth.HostCSR((1, 1), np.array([0, 1]), np.array([0], np.int32), np.array([2.0]))
+    Bm = synth.HostCSR((1, 3), np.array([0, 2]), np.array([0, 2], np.int32), np.array([1.5, -1.0]))
+    check(B, A, Bm, np.float64, exact=True, what="1x1")
+
+
+def test_repeat_gives_identical_pattern(B):
+    A = synth.varnnz_csr(4000, 4000, 0, 60, 19, np.float32, "normal", stream=0)
+    Bm = synth.varnnz_csr(4000, 4000, 0, 60, 19, np.float32, "normal", stream=1)
+    g1 = gpu_product(B, A, Bm, np.float32)
+    g2 = gpu_product(B, A, Bm, np.float32)
+    assert np.array_equal(g1.indptr, g2.indptr)
+    assert np.array_equal(g1.indices, g2.indices)
+
+
+def test_validation_flags_bad_columns(B):
+    import torch
+    A = synth.uniform_csr(100, 50, 5, 23, np.float32)
+    Bm = synth.uniform_csr(50, 60, 5, 23, np.float32, stream=1)
+    dA = B.to_device(A)
+    dB = B.to_device(Bm)
+    dB.col_idx[7] = 60  # out of range
+    plan = B.Plan(validate=True)
+    with pytest.raises(B.SpgError) as e:
+        plan.symbolic([dA], [dB])
+    assert e.value.code == B.SPG_ERR_INVALID
+    dB.col_idx[7] = 3
+    dB.row_ptr[10] = dB.row_ptr[9] - 1  # decreasing row pointer
+    with pytest.raises(B.SpgError) as e:
+        plan.symbolic([dA], [dB])
+    assert e.value.code == B.SPG_ERR_INVALID
+    torch.cuda.synchronize()
+
+
+def test_nnz_overflow_is_reported(B):
+    """A (4096 x 1, all ones) times one dense row of 2^20 columns has 2^32
+    output entries: the symbolic pass must report the int32 overflow."""
+    import torch
+    m, n = 4096, 1 << 20
+    A = synth.HostCSR((m, 1), np.arange(m + 1, dtype=np.int64), np.zeros(m, np.int32),
+                      np.ones(m, np.float32))
+    Bm = synth.HostCSR((1, n), np.array([0, n], dtype=np.int64), np.arange(n, dtype=np.int32),
+                       np.ones(n, np.float32))
+    plan = B.Plan()
+    with pytest.raises(B.SpgError) as e:
+        plan.symbolic([B.to_device(A)], [B.to_device(Bm)])
+    assert e.value.code == B.SPG_ERR_OVERFLOW
+    torch.cuda.synchronize()
+
+
+def test_capacity_mode_reports_too_small_output(B):
+    import torch
+    A = synth.uniform_csr(500, 500, 8, 29, np.float32)
+    dA = B.to_device(A)
+    plan = B.Plan()
+    rp, _ = plan.symbolic([dA], [dA], capacity=100)
+    col = torch.zeros(100, dtype=torch.int32, device="cuda")
+    vals = torch.zeros(100, dtype=torch.float32, device="cuda")
+    plan.numeric([dA], [dA], rp, 100, col=col, vals=vals)
+    assert plan.status() == B.SPG_ERR_CAPACITY
+    assert int(col.abs().sum().item()) == 0  # nothing written
+
+
+@pytest.mark.slow
+def test_uniform_2p20_fp32_full_size(B):
+    """One GPU's block share: A, B independent 2^20 x 2^20, 16 uniform columns
+    per row, FP32 in (0,1].  row_ptr checked in full against the oracle's
+    count; col_idx and values on 4096 sampled rows; row sums of C against
+    A (B 1) on every row."""
+    n = 1 << 20
+    A = synth.uniform_csr(n, n, 16, SEED + 1, np.float32, "u01", stream=0)
+    Bm = synth.uniform_csr(n, n, 16, SEED + 1, np.float32, "u01", stream=1)
+    got = gpu_product(B, A, Bm, np.float32)
+    Af = A.astype(np.float64)
+    Bf = Bm.astype(np.float64)
+    ref_rp = np.zeros(n + 1, dtype=np.int64)
+    import ctypes as C
+    L = oracle.lib()
+    rc = L.oracle_spgemm_count(C.c_int64(n), C.c_int64(n), C.c_int64(n),
+                               Af.indptr.ctypes.data_as(C.c_void_p), Af.indices.ctypes.data_as(C.c_void_p),
+                               Bf.indptr.ctypes.data_as(C.c_void_p), Bf.indices.ctypes.data_as(C.c_void_p),
+                               ref_rp.ctypes.data_as(C.c_void_p))
+    assert rc == 0
+    assert np.array_equal(got.indptr.astype(np.int64), ref_rp)
+    rows = np.sort(synth.rng_for(SEED, 5).choice(n, 4096, replace=False))
+    rows = np.concatenate([[0, n - 1], rows])
+    ref, S = oracle.spgemm(row_subset(Af, rows), Bf, with_abs=True)
+    sub = row_subset(got, rows)
+    assert_same_csr(sub, ref, S, np.float32, what="2^20 sampled rows")
+    # every row: sum_j C_ij = sum_k a_ik (sum_j b_kj)
+    rid = np.repeat(np.arange(n), np.diff(got.indptr))
+    lhs = np.bincount(rid, weights=got.data.astype(np.float64), minlength=n)
+    bsum = np.bincount(np.repeat(np.arange(n), np.diff(Bf.indptr)), weights=Bf.data, minlength=n)
+    rhs = np.bincount(np.repeat(np.arange(n), np.diff(Af.indptr)), weights=Af.data * bsum[Af.indices], minlength=n)
+    assert np.all(np.abs(lhs - rhs) <= 1e-5 * rhs + 1e-30)
