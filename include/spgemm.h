@@ -184,10 +184,10 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
 #define SPG_NBINS 16
 
 typedef struct {
-  int32_t lanes[SPG_NBINS];     /* threads cooperating on one row, per bin (power of 2) */
-  int32_t sub;                  /* lanes reading one B row together (4..64, power of 2) */
-  int32_t heavy_slots;          /* concurrent heavy rows (0 = from the workspace size) */
-  int32_t max_window;           /* largest probe displacement ranked in place */
+  int32_t lanes[SPG_NBINS];     /* threads cooperating on one row, per bin (power of 2, 8..1024) */
+  int32_t sub[SPG_NBINS];       /* threads sharing one A entry's B row, per bin (power of 2, <= 64) */
+  int32_t heavy_slots;          /* concurrent heavy rows (0 = as many as the workspace holds) */
+  int32_t max_window;           /* longest hash probe kept in the fast numeric kernel (1..32) */
 } spg_tuning;
 
 int spgemm_default_tuning(spg_tuning *t);

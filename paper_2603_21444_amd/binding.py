@@ -19,7 +19,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libspgemm.so")
+LIB_PATH = os.environ.get("SPG_LIB_PATH", os.path.join(HERE, "libspgemm.so"))
 
 SPG_OK, SPG_ERR_INVALID, SPG_ERR_SHAPE, SPG_ERR_OVERFLOW = 0, 1, 2, 3
 SPG_ERR_CAPACITY, SPG_ERR_WORKSPACE, SPG_ERR_HIP, SPG_ERR_UNSUPPORTED, SPG_ERR_ARG = 4, 5, 6, 7, 8
@@ -44,7 +44,7 @@ class SpgCsr(C.Structure):
 
 
 class SpgTuning(C.Structure):
-    _fields_ = [("lanes", C.c_int32 * SPG_NBINS), ("sub", C.c_int32),
+    _fields_ = [("lanes", C.c_int32 * SPG_NBINS), ("sub", C.c_int32 * SPG_NBINS),
                 ("heavy_slots", C.c_int32), ("max_window", C.c_int32)]
 
 
@@ -321,3 +321,35 @@ def merge(parts, plan: Plan | None = None, stream=None) -> DeviceCSR:
     rp, nnz = plan.merge_count(parts, stream=stream)
     col, vals = plan.merge_fill(parts, rp, nnz, stream=stream)
     return DeviceCSR(tuple(parts[0].shape), rp, col, vals)
+
+
+def mcl_workspace_size(n: int, topk: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().spgemm_mcl_workspace_size(n, topk, C.byref(b)), "spgemm_mcl_workspace_size")
+    return int(b.value)
+
+
+def mcl_iteration(X: DeviceCSR, r: int = 2, prune: float = 1e-4, topk: int = 1000,
+                  plan: Plan | None = None, out=None, stream=None) -> DeviceCSR:
+    """One Markov-clustering iteration on X = M^T (FP32).  `out` may hold
+    preallocated (row_ptr, col_idx, vals) of capacity n*min(topk, n)."""
+    torch = _torch()
+    plan = plan or Plan()
+    n = X.shape[0]
+    dev = X.row_ptr.device
+    need = mcl_workspace_size(n, topk)
+    if plan.ws is None or plan.ws.numel() < need:
+        plan.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    cap = n * min(topk, n)
+    if out is None:
+        out = (torch.empty(n + 1, dtype=torch.int32, device=dev),
+               torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(cap, 1), dtype=torch.float32, device=dev))
+    rp, col, vals = out
+    nnz = C.c_int64(-1)
+    x = X.spg()
+    _check(lib().spgemm_mcl_iteration(plan.h, C.byref(x), r, C.c_float(prune), topk, _ptr(rp),
+                                      _ptr(col), _ptr(vals), cap, C.byref(nnz), _ptr(plan.ws),
+                                      plan.ws.numel(), _stream(stream)), "spgemm_mcl_iteration")
+    k = int(nnz.value)
+    return DeviceCSR((n, n), rp, col[:k], vals[:k])

@@ -40,9 +40,15 @@ namespace spg {
 static std::mutex g_dev_mu;
 static std::vector<DevInfo> g_dev;
 
-static int maxbin_for(size_t lds, size_t slot_bytes, size_t extra) {
+// Largest bin whose table fits one block (one row per block, 1024 lanes).
+static int maxbin_for(size_t lds, int pass, size_t vbytes) {
   int b = kMaxLdsBin;
-  while (b > 1 && (size_t)(bin_slots(b) + kTail) * slot_bytes + extra > lds) --b;
+  auto bytes = [&](int bb) {
+    if (pass == 0) return sym_lds_bytes(bb, 1024);
+    if (pass == 1) return num_lds_bytes(bb, 1024, vbytes, false);
+    return mcl_lds_bytes(bb, 1024);
+  };
+  while (b > 1 && bytes(b) > lds) --b;
   return b;
 }
 
@@ -66,10 +72,13 @@ const DevInfo &dev_info() {
     d.lds_per_cu = (size_t)v;
   if (d.lds_per_cu < d.lds_per_block) d.lds_per_cu = d.lds_per_block;
   // the largest table of each pass that fits one block's LDS
-  d.sym_maxbin = maxbin_for(d.lds_per_block, 4, 64);
-  d.num_maxbin_f32 = maxbin_for(d.lds_per_block, 8, 128);
-  d.num_maxbin_f64 = maxbin_for(d.lds_per_block, 12, 128);
+  d.sym_maxbin = maxbin_for(d.lds_per_block, 0, 0);
+  d.num_maxbin_f32 = maxbin_for(d.lds_per_block, 1, 4);
+  d.num_maxbin_f64 = maxbin_for(d.lds_per_block, 1, 8);
+  d.mcl_maxbin = maxbin_for(d.lds_per_block, 2, 4);
   (void)configure_lds_limits(d.lds_per_block);
+  (void)configure_backward_lds(d.lds_per_block);
+  (void)configure_mcl_lds(d.lds_per_block);
   (void)hipGetLastError();
   g_dev.push_back(d);
   return g_dev.back();
@@ -119,20 +128,23 @@ spg_tuning default_tuning() {
   spg_tuning t{};
   // lanes per row for bins of at most 16, 32, ..., 16384 products or entries
   const int lanes[kNB] = {0, 8, 16, 16, 32, 64, 128, 256, 256, 512, 1024, 1024, 1024, 1024, 1024, 1024};
-  for (int b = 0; b < kNB; ++b) t.lanes[b] = lanes[b];
-  t.sub = 16;
+  for (int b = 0; b < kNB; ++b) {
+    t.lanes[b] = lanes[b];
+    t.sub[b] = 16;
+  }
   t.heavy_slots = 0;
-  t.max_window = 32;
+  t.max_window = kTail;
   return t;
 }
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 int check_tuning(const spg_tuning &t) {
-  for (int b = 1; b < kNB; ++b)
-    if (!pow2(t.lanes[b]) || t.lanes[b] > 1024) return SPG_ERR_ARG;
-  if (!pow2(t.sub) || t.sub < 1 || t.sub > 64) return SPG_ERR_ARG;
-  if (t.heavy_slots < 0 || t.max_window < 1) return SPG_ERR_ARG;
+  for (int b = 1; b < kNB; ++b) {
+    if (!pow2(t.lanes[b]) || t.lanes[b] < 8 || t.lanes[b] > 1024) return SPG_ERR_ARG;
+    if (!pow2(t.sub[b]) || t.sub[b] > 64) return SPG_ERR_ARG;
+  }
+  if (t.heavy_slots < 0 || t.max_window < 1 || t.max_window > kTail) return SPG_ERR_ARG;
   return SPG_OK;
 }
 
@@ -164,8 +176,10 @@ BinPlan make_binplan(spg_plan p, int maxbin, bool counts_known, const int *count
   bp.known = counts_known;
   if (counts_known)
     for (int b = 0; b < kNB; ++b) bp.count[b] = counts[b];
-  for (int b = 0; b < kNB; ++b) bp.lanes[b] = p->tun.lanes[b];
-  bp.sub = p->tun.sub;
+  for (int b = 0; b < kNB; ++b) {
+    bp.lanes[b] = p->tun.lanes[b];
+    bp.sub[b] = p->tun.sub[b];
+  }
   bp.maxbin = maxbin;
   bp.heavy_slots = p->L.heavy_slots;
   bp.n = p->n;
@@ -453,6 +467,132 @@ int spgemm_merge(spg_plan plan, int32_t K, const spg_csr *P, spg_dtype dtype,
   rc = check_values(K, nullptr, P, true);
   if (rc) return rc;
   return run_numeric(plan, pr, dtype, C_col_idx, C_vals, st);
+}
+
+int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg_csr *dC,
+                    spg_dtype dtype, void *dA_vals, void *dB_vals, void *stream) {
+  if (!plan || !A || !B || !dC) return SPG_ERR_ARG;
+  if (!plan->sym_done || plan->merge_mode || plan->K != 1) return SPG_ERR_ARG;
+  if (dtype != SPG_F32 && dtype != SPG_F64) return SPG_ERR_ARG;
+  Problem pr;
+  int rc = fill_parts(pr, 1, A, B, false);
+  if (rc) return rc;
+  if (!same_operands(plan, 1, A, B)) return SPG_ERR_SHAPE;
+  rc = check_values(1, A, B, false);
+  if (rc) return rc;
+  if (dC->nrows != plan->m || dC->ncols != plan->n) return SPG_ERR_SHAPE;
+  if (plan->nnz >= 0 && dC->nnz != plan->nnz) return SPG_ERR_SHAPE;
+  if (!dC->row_ptr || (dC->nnz > 0 && (!dC->col_idx || !dC->vals))) return SPG_ERR_ARG;
+  if (!dA_vals && !dB_vals) return SPG_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevInfo &D = dev_info();
+  char *ws = plan->ws;
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  Problem *dpr = reinterpret_cast<Problem *>(ws + plan->L.problem);
+  hipError_t e = launch_setup(pr, dpr, hdr, false, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  const int maxbin = dtype == SPG_F64 ? D.num_maxbin_f64 : D.num_maxbin_f32;
+  BinPlan bp = make_binplan(plan, maxbin, plan->counts_known, plan->num_count);
+  e = launch_backward(dpr, bp, plan->L, ws, dC->row_ptr, dC->col_idx, dC->vals, dA_vals,
+                      A->nnz, dB_vals, B->nnz, (int)dtype, st);
+  plan->stream = st;
+  return hip_status(e);
+}
+
+static void mcl_layout(int32_t n, int32_t topk, WsLayout &L, size_t &pcol, size_t &pval,
+                       size_t &total, int &cap) {
+  L = ws_layout(n, n, default_heavy_slots(n));
+  cap = topk < n ? topk : n;
+  if (cap < 1) cap = 1;
+  const size_t pad = (size_t)std::max(n, 1) * (size_t)cap;
+  pcol = (L.total + 255) & ~(size_t)255;
+  pval = (pcol + 4 * pad + 255) & ~(size_t)255;
+  total = pval + 4 * pad;
+}
+
+int spgemm_mcl_workspace_size(int32_t n, int32_t topk, size_t *bytes) {
+  if (!bytes || n < 0 || topk < 1) return SPG_ERR_ARG;
+  WsLayout L;
+  size_t pc, pv, tot;
+  int cap;
+  mcl_layout(n, topk, L, pc, pv, tot, cap);
+  *bytes = tot;
+  return SPG_OK;
+}
+
+int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune, int32_t topk,
+                         int32_t *Y_row_ptr, int32_t *Y_col_idx, float *Y_vals, int64_t capacity,
+                         int64_t *Y_nnz_host, void *workspace, size_t ws_bytes, void *stream) {
+  if (!plan || !X || !Y_row_ptr) return SPG_ERR_ARG;
+  if (X->nrows != X->ncols) return SPG_ERR_SHAPE;
+  if (r < 1 || r > 8 || topk < 1 || !(prune >= 0.f) || !(prune < 1e30f)) return SPG_ERR_ARG;
+  if (X->ncols > kLdsBitmapCols) return SPG_ERR_UNSUPPORTED;  // heavy rows keep a bitmap in LDS
+  if (!Y_nnz_host && capacity < 0) return SPG_ERR_ARG;
+  if (X->nnz > 0 && (!X->col_idx || !X->vals)) return SPG_ERR_ARG;
+  const int n = X->nrows;
+  WsLayout L;
+  size_t pcol_off, pval_off, total;
+  int cap;
+  mcl_layout(n, topk, L, pcol_off, pval_off, total, cap);
+  if (!workspace || ws_bytes < total) return SPG_ERR_WORKSPACE;
+  Problem pr;
+  int rc = fill_parts(pr, 1, X, X, false);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  plan->sym_done = false;
+  plan->counts_known = false;
+  plan->ws = static_cast<char *>(workspace);
+  plan->ws_bytes = ws_bytes;
+  plan->L = L;
+  plan->stream = st;
+  plan->m = plan->n = n;
+  plan->nnz = -1;
+  const DevInfo &D = dev_info();
+  char *ws = plan->ws;
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  Problem *dpr = reinterpret_cast<Problem *>(ws + L.problem);
+  int32_t *pcol = reinterpret_cast<int32_t *>(ws + pcol_off);
+  float *pval = reinterpret_cast<float *>(ws + pval_off);
+  hipError_t e = launch_setup(pr, dpr, hdr, true, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  const bool eager = Y_nnz_host != nullptr;
+  if (plan->flags & SPG_FLAG_VALIDATE) {
+    launch_validate(X->row_ptr, X->col_idx, n, n, X->nnz, hdr, st);
+    if (eager) {
+      rc = read_header(plan, st);
+      if (rc) return rc;
+      rc = status_from_bits(plan->host_hdr->status);
+      if (rc) return rc;
+    }
+  }
+  e = launch_binning(dpr, nullptr, 0, n, D.mcl_maxbin, L, ws, Y_row_ptr, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  BinPlan bp;
+  if (eager) {
+    rc = read_header(plan, st);
+    if (rc) return rc;
+    rc = status_from_bits(plan->host_hdr->status);
+    if (rc) return rc;
+    bp = make_binplan(plan, D.mcl_maxbin, true, plan->host_hdr->bin_count);
+  } else {
+    bp = make_binplan(plan, D.mcl_maxbin, false, nullptr);
+  }
+  e = launch_mcl(dpr, bp, L, ws, r, prune, topk, cap, pcol, pval, Y_row_ptr, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  e = launch_scan(Y_row_ptr, n, eager ? -1 : capacity, L, ws, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  if (eager) {
+    rc = read_header(plan, st);
+    if (rc) return rc;
+    rc = status_from_bits(plan->host_hdr->status);
+    if (rc) return rc;
+    plan->nnz = plan->host_hdr->nnz_total;
+    plan->products = plan->host_hdr->products_total;
+    *Y_nnz_host = plan->nnz;
+    if (plan->nnz > 0 && (!Y_col_idx || !Y_vals)) return SPG_ERR_ARG;
+  }
+  e = launch_mcl_compact(n, cap, Y_row_ptr, pcol, pval, Y_col_idx, Y_vals, hdr, st);
+  return hip_status(e);
 }
 
 }  // extern "C"

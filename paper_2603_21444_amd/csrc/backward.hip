@@ -1,0 +1,278 @@
+// Backward pass of C = A B at fixed sparsity (a9): for a loss L with
+// W = dL/dC on S(C),
+//   dA_ik = sum_{j in S(B)_k} W_ij b_kj     for (i,k) in S(A)
+//   dB_kj = sum_{i : k in S(A)_i} a_ik W_ij  for (k,j) in S(B).
+// Not in the paper; the definition is the derivative of the bilinear map
+// (A, B) -> A B restricted to the given patterns.
+//
+// One pass over the forward product set.  Per row i of C the W values go
+// into an LDS hash keyed by column (rows beyond the LDS tables use a dense
+// row in the heavy-slot scratch instead).  Every product (p, q) looks up
+// w = W_i,col(q); dA_p collects w * b_q in an LDS accumulator of its A
+// entry, and a_p * w is added to dB_q with a device-scope atomic, so the
+// summation order of a dB entry is not fixed.
+#include <vector>
+
+#include "internal.hpp"
+#include "rowops.hpp"
+
+namespace spg {
+
+template <typename VT>
+__global__ void k_fill_zero(VT *p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
+    p[t] = VT(0);
+}
+
+// Products of row i, S lanes per A entry, with the entry's staged slot e
+// passed to f(col, b, e).  Chunks of G entries of the A row are staged in
+// LDS; `done(c0, nE)` runs after each chunk (group-synchronised).
+template <bool BLOCK, int G, typename VT, typename F, typename D>
+__device__ __forceinline__ void for_each_product_e(const Part &P, int i, int l, int lS, int *sb,
+                                                   int *sl, VT *sa, VT *sd, F &&f, D &&done) {
+  const int S = 1 << lS;
+  const int ES = G >> lS;
+  const int sg = l >> lS;
+  const int q0 = l & (S - 1);
+  const SPG_GLOBAL int32_t *brp = gp(P.brp);
+  const SPG_GLOBAL int32_t *bcol = gp(P.bcol);
+  const SPG_GLOBAL VT *bval = gp(static_cast<const VT *>(P.bval));
+  const int as = gp(P.arp)[i], nA = gp(P.arp)[i + 1] - as;
+  for (int c0 = 0; c0 < nA; c0 += G) {
+    const int e = c0 + l;
+    if (e < nA) {
+      const int r = gp(P.acol)[as + e];
+      const int b0 = brp[r];
+      sb[l] = b0;
+      sl[l] = brp[r + 1] - b0;
+      sa[l] = gp(static_cast<const VT *>(P.aval))[as + e];
+      sd[l] = VT(0);
+    }
+    const int nE = min(G, nA - c0);
+    group_sync<BLOCK>();
+    for (int ee = sg; ee < nE; ee += ES) {
+      const int len = sl[ee];
+      for (int q = q0; q < len; q += S) {
+        const int idx = sb[ee] + q;
+        f(bcol[idx], bval[idx], idx, ee);
+      }
+    }
+    group_sync<BLOCK>();
+    done(as + c0, nE);
+    group_sync<BLOCK>();
+  }
+}
+
+template <int G>
+struct BGeom {
+  static constexpr bool BLOCK = G > kWave;
+  static constexpr int WG = BLOCK ? G : 256;
+  static constexpr int R = WG / G;
+};
+
+template <int G, typename VT>
+__global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
+    const Problem *__restrict__ pr, const int32_t *__restrict__ rows,
+    WsHeader *__restrict__ hdr, int bin, int lS, int log2T, const int32_t *__restrict__ crp,
+    const int32_t *__restrict__ ccol, const VT *__restrict__ w, VT *__restrict__ dA,
+    VT *__restrict__ dB) {
+  using GM = BGeom<G>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int T = 1 << log2T;
+  const int rslot = threadIdx.x / G, l = threadIdx.x % G;
+  VT *wv = reinterpret_cast<VT *>(smem_raw) + (size_t)rslot * T;
+  VT *sa = reinterpret_cast<VT *>(smem_raw) + (size_t)GM::R * T + rslot * G;
+  VT *sd = sa + (size_t)GM::R * G;
+  int *key = reinterpret_cast<int *>(reinterpret_cast<VT *>(smem_raw) + (size_t)GM::R * (T + 2 * G)) +
+             (size_t)rslot * T;
+  int *sb = reinterpret_cast<int *>(reinterpret_cast<VT *>(smem_raw) + (size_t)GM::R * (T + 2 * G)) +
+            (size_t)GM::R * T + rslot * G;
+  int *sl = sb + (size_t)GM::R * G;
+  if (hdr->status) return;
+  const int count = hdr->bin_count[bin];
+  const int start = hdr->bin_start[bin];
+  const Part &P = pr->part[0];
+  for (int ri = blockIdx.x * GM::R + rslot; ri < count; ri += gridDim.x * GM::R) {
+    int i = rows[start + ri];
+    if (G >= kWave) i = __builtin_amdgcn_readfirstlane(i);
+    for (int s = l; s < T; s += G) key[s] = kEmpty;
+    group_sync<GM::BLOCK>();
+    const int rs = crp[i], re = crp[i + 1];
+    for (int t = rs + l; t < re; t += G) {
+      const int col = ccol[t];
+      uint32_t h = scramble_slot((uint32_t)col, log2T);
+      int probes = 0;
+      while (atomicCAS(&key[h], kEmpty, col) != kEmpty) {
+        if (++probes > T) {  // row longer than the plan's C row: pattern mismatch
+          atomicOr(&hdr->status, kStatInvalid);
+          break;
+        }
+        h = (h + 1) & (T - 1);
+      }
+      if (probes <= T) wv[h] = w[t];
+    }
+    group_sync<GM::BLOCK>();
+    for_each_product_e<GM::BLOCK, G, VT>(
+        P, i, l, lS, sb, sl, sa, sd,
+        [&](int col, VT b, int idx, int ee) {
+          uint32_t h = scramble_slot((uint32_t)col, log2T);
+          int probes = 0;
+          int k2;
+          while ((k2 = key[h]) != col) {
+            if (k2 == kEmpty || ++probes > T) {  // product outside the given pattern
+              atomicOr(&hdr->status, kStatInvalid);
+              return;
+            }
+            h = (h + 1) & (T - 1);
+          }
+          const VT wij = wv[h];
+          if (dA) lds_add(&sd[ee], wij * b);
+          if (dB) global_add(&dB[idx], sa[ee] * wij);
+        },
+        [&](int p0, int nE) {
+          if (dA && l < nE) dA[p0 + l] = sd[l];
+        });
+  }
+}
+
+// Heavy rows: W row scattered densely into the slot's scratch row.
+template <typename VT>
+__global__ __launch_bounds__(1024) void k_bwd_heavy(const Problem *__restrict__ pr,
+                                                    const int32_t *__restrict__ rows,
+                                                    WsHeader *__restrict__ hdr, int blo, int lS,
+                                                    VT *gacc, const int32_t *__restrict__ crp,
+                                                    const int32_t *__restrict__ ccol,
+                                                    const VT *__restrict__ w,
+                                                    VT *__restrict__ dA, VT *__restrict__ dB) {
+  __shared__ int sb[1024], sl[1024];
+  __shared__ VT sa[1024], sd[1024];
+  const int n = pr->n;
+  VT *dense = gacc + (size_t)blockIdx.x * n;
+  if (hdr->status) return;
+  const int start = hdr->bin_start[blo];
+  const int count = hdr->bin_start[kHeavyBin + 1] - start;
+  const int tid = threadIdx.x;
+  const Part &P = pr->part[0];
+  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+    const int i = rows[start + ri];
+    const int rs = crp[i], re = crp[i + 1];
+    for (int t = rs + tid; t < re; t += 1024) dense[ccol[t]] = w[t];
+    __threadfence();
+    __syncthreads();
+    for_each_product_e<true, 1024, VT>(
+        P, i, tid, lS, sb, sl, sa, sd,
+        [&](int col, VT b, int idx, int ee) {
+          const VT wij = dense[col];
+          if (dA) lds_add(&sd[ee], wij * b);
+          if (dB) global_add(&dB[idx], sa[ee] * wij);
+        },
+        [&](int p0, int nE) {
+          if (dA && tid < nE) dA[p0 + tid] = sd[tid];
+        });
+    __threadfence();
+    __syncthreads();
+  }
+}
+
+template <int G, typename VT>
+static void bwd_launch(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin, int lS,
+                       int log2T, const int32_t *crp, const int32_t *ccol, const VT *w, VT *dA,
+                       VT *dB, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_bwd_rows<G, VT>), dim3(grid), dim3(BGeom<G>::WG), lds, st, dpr, rows, hdr,
+                     bin, lS, log2T, crp, ccol, w, dA, dB);
+}
+
+size_t bwd_lds_bytes(int b, int G, size_t vbytes) {
+  const int WG = G <= kWave ? 256 : G, R = WG / G;
+  const size_t T = (size_t)bin_slots(b);
+  return (size_t)R * T * (vbytes + 4) + (size_t)R * G * (2 * vbytes + 8);
+}
+
+template <typename VT>
+static hipError_t backward_impl(const Problem *dpr, const BinPlan &bp, const WsLayout &L,
+                                char *ws, const int32_t *crp, const int32_t *ccol, const VT *w,
+                                VT *dA, int64_t nnzA, VT *dB, int64_t nnzB, hipStream_t st) {
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  const int32_t *rows = reinterpret_cast<const int32_t *>(ws + L.rows);
+  const DevInfo &D = dev_info();
+  if (dA && nnzA > 0)
+    hipLaunchKernelGGL(k_fill_zero<VT>, dim3(D.cus * 4), dim3(256), 0, st, dA, nnzA);
+  if (dB && nnzB > 0)
+    hipLaunchKernelGGL(k_fill_zero<VT>, dim3(D.cus * 4), dim3(256), 0, st, dB, nnzB);
+  for (int b = 1; b <= bp.maxbin; ++b) {
+    if (bp.known && bp.count[b] == 0) continue;
+    int G = bp.lanes[b];
+    while (G < 1024 && bwd_lds_bytes(b, G, sizeof(VT)) > D.lds_per_block) G *= 2;
+    const int WG = G <= kWave ? 256 : G;
+    const int R = WG / G;
+    const size_t lds = bwd_lds_bytes(b, G, sizeof(VT));
+    int cap = D.cus * (int)std::max<size_t>(1, std::min<size_t>(D.lds_per_cu / lds, 2048 / WG));
+    int grid = cap;
+    if (bp.known) grid = std::min(cap, (bp.count[b] + R - 1) / R);
+    int lt = 0;
+    while ((1 << lt) < bin_slots(b)) ++lt;
+    int S = bp.sub[b] > 0 ? bp.sub[b] : 16;
+    if (S > G) S = G;
+    int lS = 0;
+    while ((1 << lS) < S) ++lS;
+    switch (G) {
+#define SPG_BWD_CASE(g) \
+  case g: bwd_launch<g, VT>(dpr, rows, hdr, b, lS, lt, crp, ccol, w, dA, dB, grid, lds, st); break;
+      SPG_BWD_CASE(8)
+      SPG_BWD_CASE(16)
+      SPG_BWD_CASE(32)
+      SPG_BWD_CASE(64)
+      SPG_BWD_CASE(128)
+      SPG_BWD_CASE(256)
+      SPG_BWD_CASE(512)
+      default: bwd_launch<1024, VT>(dpr, rows, hdr, b, lS, lt, crp, ccol, w, dA, dB, grid, lds, st);
+#undef SPG_BWD_CASE
+    }
+  }
+  int hc = -1;
+  if (bp.known) {
+    hc = 0;
+    for (int b = bp.maxbin + 1; b <= kHeavyBin; ++b) hc += bp.count[b];
+  }
+  if (hc != 0) {
+    int grid = bp.heavy_slots;
+    if (hc > 0 && hc < grid) grid = hc;
+    int S = bp.sub[kHeavyBin] > 0 ? bp.sub[kHeavyBin] : 16;
+    int lS = 0;
+    while ((1 << lS) < S) ++lS;
+    hipLaunchKernelGGL(k_bwd_heavy<VT>, dim3(grid), dim3(1024), 0, st, dpr, rows, hdr,
+                       bp.maxbin + 1, lS, reinterpret_cast<VT *>(ws + L.heavyacc), crp, ccol, w,
+                       dA, dB);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
+                           const int32_t *crp, const int32_t *ccol, const void *w, void *dA,
+                           int64_t nnzA, void *dB, int64_t nnzB, int dtype, hipStream_t st) {
+  if (dtype == SPG_F64)
+    return backward_impl<double>(dpr, bp, L, ws, crp, ccol, static_cast<const double *>(w),
+                                 static_cast<double *>(dA), nnzA, static_cast<double *>(dB), nnzB,
+                                 st);
+  return backward_impl<float>(dpr, bp, L, ws, crp, ccol, static_cast<const float *>(w),
+                              static_cast<float *>(dA), nnzA, static_cast<float *>(dB), nnzB, st);
+}
+
+hipError_t configure_backward_lds(size_t lds_max) {
+  const void *ks[] = {
+#define SPG_BWD_K(g) reinterpret_cast<const void *>(&k_bwd_rows<g, float>), \
+                     reinterpret_cast<const void *>(&k_bwd_rows<g, double>),
+      SPG_BWD_K(8) SPG_BWD_K(16) SPG_BWD_K(32) SPG_BWD_K(64) SPG_BWD_K(128) SPG_BWD_K(256)
+      SPG_BWD_K(512) SPG_BWD_K(1024)
+#undef SPG_BWD_K
+  };
+  for (const void *k : ks) {
+    hipError_t e =
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace spg

@@ -1,0 +1,288 @@
+// Kernels around the row kernels of the local product C = sum_k A_k B_k
+// (K = 1: C = A B, paper §2) on gfx950: problem setup, optional operand
+// validation, products per row and row binning, and the scan of row counts
+// into the CSR row pointer of C.
+//
+// Every kernel reads the operand descriptors from a device copy of the
+// Problem (scalar loads; the copy is made by k_setup in the same stream) and
+// the row lists and bin counts from the workspace header, so the same
+// launches work eagerly and inside a captured graph.  Kernels with row lists
+// loop over them grid-stride style, so any grid size is correct.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace spg {
+
+// ---------------------------------------------------------------------------
+// Setup: copy the problem into the workspace, clear the header.
+__global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset) {
+  if (threadIdx.x == 0) *dst = pr;
+  if (reset && threadIdx.x < kNB) {
+    hdr->bin_count[threadIdx.x] = 0;
+    hdr->bin_start[threadIdx.x] = 0;
+  }
+  if (reset && threadIdx.x == 0) {
+    hdr->status = 0;
+    hdr->nnz_total = 0;
+    hdr->products_total = 0;
+    hdr->bin_start[kNB] = 0;
+  }
+  if (threadIdx.x == 0) {
+    hdr->fallback_count = 0;
+    hdr->heavy_cursor = 0;
+  }
+}
+
+// Optional validation of one CSR operand: row_ptr[0] == 0, non-decreasing,
+// row_ptr[rows] == nnz, columns in range.
+__global__ void k_validate(const int32_t *rp, const int32_t *col, int rows, int ncols,
+                           int64_t nnz, WsHeader *hdr) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  if (t == 0) bad = bad || rp[0] != 0 || (int64_t)rp[rows] != nnz;
+  for (int64_t i = t; i < rows; i += stride) bad = bad || rp[i + 1] < rp[i];
+  for (int64_t p = t; p < nnz; p += stride) bad = bad || col[p] < 0 || col[p] >= ncols;
+  if (bad) atomicOr(&hdr->status, kStatInvalid);
+}
+
+// ---------------------------------------------------------------------------
+// a1/a2: row key (products per row, or nnz of a C row) and bin id; per-block
+// bin histogram.  One thread per row, 256 rows per block.
+constexpr int kBinBlock = 256;
+
+__global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict__ pr,
+                                                      const int32_t *__restrict__ crp,
+                                                      int mode, int maxbin, uint8_t *binid,
+                                                      int32_t *blockhist, int32_t *cnt_zero,
+                                                      WsHeader *hdr) {
+  __shared__ int hist[kNB];
+  __shared__ long long psum[kBinBlock / kWave];
+  if (hdr->status) return;  // invalid operands or overflow: touch nothing
+  if (threadIdx.x < kNB) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int m = pr->m;
+  const int i = blockIdx.x * kBinBlock + threadIdx.x;
+  int64_t key = 0;
+  if (i < m) {
+    if (mode == 0) {
+      const int K = pr->K;
+      for (int k = 0; k < K; ++k) {
+        const Part &P = pr->part[k];
+        int as, ae;
+        a_row(P, i, as, ae);
+        for (int p = as; p < ae; ++p) {
+          int r = a_entry_row(P, i, p);
+          key += gp(P.brp)[r + 1] - gp(P.brp)[r];
+        }
+      }
+      if (key == 0) cnt_zero[i] = 0;
+    } else {
+      key = crp[i + 1] - crp[i];
+    }
+    int b = bin_of(key, maxbin);
+    binid[i] = (uint8_t)b;
+    atomicAdd(&hist[b], 1);
+  }
+  if (mode == 0) {
+    // block sum of products -> header (int64)
+    long long v = key;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane_id() == 0) psum[threadIdx.x / kWave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNB) blockhist[(int64_t)blockIdx.x * kNB + threadIdx.x] = hist[threadIdx.x];
+  if (mode == 0 && threadIdx.x == 0) {
+    long long s = 0;
+    for (int w = 0; w < kBinBlock / kWave; ++w) s += psum[w];
+    atomicAdd((unsigned long long *)&hdr->products_total, (unsigned long long)s);
+  }
+}
+
+// Exclusive scan of the per-block histograms in bin-major order (one block).
+__global__ __launch_bounds__(1024) void k_binscan(int32_t *blockhist, int nblk, WsHeader *hdr) {
+  __shared__ int wsum[16];
+  __shared__ int carry;
+  const int tid = threadIdx.x;
+  int base_all = 0;
+  for (int b = 0; b < kNB; ++b) {
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nblk; c0 += 1024) {
+      int idx = c0 + tid;
+      int v = idx < nblk ? blockhist[(int64_t)idx * kNB + b] : 0;
+      // inclusive wave scan
+      int x = v;
+      for (int off = 1; off < kWave; off <<= 1) {
+        int y = __shfl_up(x, off);
+        if (lane_id() >= off) x += y;
+      }
+      if (lane_id() == kWave - 1) wsum[tid / kWave] = x;
+      __syncthreads();
+      int wpre = 0, tot = 0;
+      for (int w = 0; w < 16; ++w) {
+        if (w < tid / kWave) wpre += wsum[w];
+        tot += wsum[w];
+      }
+      int excl = carry + wpre + x - v;
+      if (idx < nblk) blockhist[(int64_t)idx * kNB + b] = base_all + excl;
+      __syncthreads();
+      if (tid == 0) carry += tot;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      hdr->bin_count[b] = carry;
+      hdr->bin_start[b] = base_all;
+    }
+    base_all += carry;
+    __syncthreads();
+  }
+  if (tid == 0) hdr->bin_start[kNB] = base_all;
+}
+
+// Stable scatter of row ids into the per-bin lists.
+__global__ __launch_bounds__(kBinBlock) void k_binscatter(const uint8_t *binid, int m,
+                                                          const int32_t *blockoff,
+                                                          int32_t *rows, const WsHeader *hdr) {
+  __shared__ int wcnt[kBinBlock / kWave][kNB];
+  if (hdr->status) return;
+  const int i = blockIdx.x * kBinBlock + threadIdx.x;
+  const int w = threadIdx.x / kWave;
+  const int b = i < m ? binid[i] : -1;
+  int myrank = 0;
+  for (int bb = 0; bb < kNB; ++bb) {
+    uint64_t mask = __ballot(b == bb);
+    if (b == bb) myrank = mbcnt(mask);
+    if (lane_id() == 0) wcnt[w][bb] = __popcll(mask);
+  }
+  __syncthreads();
+  if (i < m) {
+    int off = blockoff[(int64_t)blockIdx.x * kNB + b];
+    for (int ww = 0; ww < w; ++ww) off += wcnt[ww][b];
+    rows[off + myrank] = i;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a3 scan: in-place exclusive scan of per-row counts into row_ptr[0..m]
+// (int64 running total; > 2^31-1 raises the overflow status).
+constexpr int kScanTile = 2048;  // 256 threads x 8
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const int32_t *cnt, int m, int64_t *part) {
+  __shared__ long long ws[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  long long s = 0;
+  for (int j = 0; j < 8; ++j) {
+    const int64_t i = base + j * 256 + threadIdx.x;
+    if (i < m) s += cnt[i];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane_id() == 0) ws[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_mid(int64_t *part, int nparts, int64_t capacity,
+                                                   WsHeader *hdr) {
+  __shared__ long long wsum[16];
+  __shared__ long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nparts; c0 += 1024) {
+    const int idx = c0 + threadIdx.x;
+    const long long v = idx < nparts ? part[idx] : 0;
+    long long x = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+      long long y = __shfl_up(x, off);
+      if (lane_id() >= off) x += y;
+    }
+    if (lane_id() == kWave - 1) wsum[threadIdx.x / kWave] = x;
+    __syncthreads();
+    long long wpre = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < (int)threadIdx.x / kWave) wpre += wsum[w];
+      tot += wsum[w];
+    }
+    if (idx < nparts) part[idx] = carry + wpre + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    hdr->nnz_total = carry;
+    int st = 0;
+    if (carry > 0x7fffffffLL) st |= kStatOverflow;
+    if (capacity >= 0 && carry > capacity) st |= kStatCapacity;
+    if (st) atomicOr(&hdr->status, st);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(int32_t *rp, int m, const int64_t *part,
+                                                    const WsHeader *hdr) {
+  __shared__ long long wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  // each thread owns 8 consecutive entries
+  const int64_t i0 = base + threadIdx.x * 8;
+  int v[8];
+  long long s = 0;
+  for (int j = 0; j < 8; ++j) {
+    v[j] = (i0 + j < m) ? rp[i0 + j] : 0;
+    s += v[j];
+  }
+  long long x = s;
+  for (int off = 1; off < kWave; off <<= 1) {
+    long long y = __shfl_up(x, off);
+    if (lane_id() >= off) x += y;
+  }
+  if (lane_id() == kWave - 1) wsum[threadIdx.x / kWave] = x;
+  __syncthreads();
+  long long wpre = 0;
+  for (int w = 0; w < (int)threadIdx.x / kWave; ++w) wpre += wsum[w];
+  int64_t run = part[blockIdx.x] + wpre + x - s;
+  for (int j = 0; j < 8; ++j) {
+    if (i0 + j < m) rp[i0 + j] = (int32_t)run;
+    run += v[j];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) rp[m] = (int32_t)hdr->nnz_total;
+}
+
+// Host launchers.
+
+hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool reset,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, pr, dst, hdr, reset ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const int32_t *rp, const int32_t *col, int rows, int ncols,
+                           int64_t nnz, WsHeader *hdr, hipStream_t st) {
+  hipLaunchKernelGGL(k_validate, dim3(256), dim3(256), 0, st, rp, col, rows, ncols, nnz, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_binning(const Problem *dpr, const int32_t *crp, int mode, int m, int maxbin,
+                          const WsLayout &L, char *ws, int32_t *cnt_zero, hipStream_t st) {
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  const int nblk = m == 0 ? 1 : (m + kBinBlock - 1) / kBinBlock;
+  uint8_t *binid = reinterpret_cast<uint8_t *>(ws + L.binid);
+  int32_t *bh = reinterpret_cast<int32_t *>(ws + L.blockhist);
+  int32_t *rows = reinterpret_cast<int32_t *>(ws + L.rows);
+  hipLaunchKernelGGL(k_rowkey, dim3(nblk), dim3(kBinBlock), 0, st, dpr, crp, mode, maxbin,
+                     binid, bh, cnt_zero, hdr);
+  hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, bh, nblk, hdr);
+  hipLaunchKernelGGL(k_binscatter, dim3(nblk), dim3(kBinBlock), 0, st, binid, m, bh, rows, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(int32_t *rp, int m, int64_t capacity, const WsLayout &L, char *ws,
+                       hipStream_t st) {
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  int64_t *part = reinterpret_cast<int64_t *>(ws + L.scanpart);
+  const int nparts = m == 0 ? 1 : (m + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(256), 0, st, rp, m, part);
+  hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, part, nparts, capacity, hdr);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(256), 0, st, rp, m, part, hdr);
+  return hipGetLastError();
+}
+
+}  // namespace spg

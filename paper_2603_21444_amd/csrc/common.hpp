@@ -13,7 +13,7 @@ constexpr int kEmpty = -1;          // empty hash slot (column indices are >= 0)
 constexpr int kNB = SPG_NBINS;      // row bins
 constexpr int kHeavyBin = 12;       // rows beyond every LDS table
 constexpr int kMaxLdsBin = 11;      // largest LDS bin index
-constexpr int kTail = 64;           // extra slots after a table: probes never wrap early
+constexpr int kTail = 32;           // slots after a table: a probe walks at most kTail past it
 constexpr int kLdsBitmapCols = 1 << 20;  // columns a heavy row can mark in LDS (128 KiB)
 
 // Status bits raised by kernels in the workspace header.
@@ -63,6 +63,20 @@ struct WsHeader {
   int32_t heavy_cursor;
 };
 
+// Operand arrays are read through global-address-space pointers: the
+// pointers come from memory (the device copy of the Problem), and without
+// the cast the compiler would emit flat loads, which also hold up every LDS
+// wait and cannot be reordered around LDS atomics.
+#define SPG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const SPG_GLOBAL T *gp(const T *p) {
+  return (const SPG_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ SPG_GLOBAL T *gpw(T *p) {
+  return (SPG_GLOBAL T *)p;
+}
+
 __device__ inline int lane_id() { return __lane_id(); }
 
 // Number of set bits of `mask` strictly below this lane.
@@ -105,17 +119,17 @@ __device__ inline T ld_val(const void *p, int64_t i) {
 // Entries of row i of A_k: [start, end) into acol/aval (identity: one entry).
 __device__ inline void a_row(const Part &P, int i, int &s, int &e) {
   if (P.a_identity) { s = 0; e = 1; }
-  else { s = P.arp[i]; e = P.arp[i + 1]; }
+  else { s = gp(P.arp)[i]; e = gp(P.arp)[i + 1]; }
 }
 
 template <typename VT>
 __device__ inline void a_entry(const Part &P, int i, int p, int &brow, VT &a) {
   if (P.a_identity) { brow = i; a = VT(1); }
-  else { brow = P.acol[p]; a = ld_val<VT>(P.aval, p); }
+  else { brow = gp(P.acol)[p]; a = gp(static_cast<const VT *>(P.aval))[p]; }
 }
 
 __device__ inline int a_entry_row(const Part &P, int i, int p) {
-  return P.a_identity ? i : P.acol[p];
+  return P.a_identity ? i : gp(P.acol)[p];
 }
 
 }  // namespace spg

@@ -17,6 +17,7 @@ struct DevInfo {
   int sym_maxbin = kMaxLdsBin;   // largest LDS bin of the symbolic pass
   int num_maxbin_f32 = 10;       // largest LDS bin of the FP32 numeric pass
   int num_maxbin_f64 = 9;        // largest LDS bin of the FP64 numeric pass
+  int mcl_maxbin = 10;           // largest LDS bin of the MCL iteration
 };
 
 const DevInfo &dev_info();
@@ -31,12 +32,12 @@ WsLayout ws_layout(int64_t m, int64_t n, int heavy_slots);
 int default_heavy_slots(int64_t n);
 
 // What a pass needs to know about the bins: counts when read back (eager),
-// lanes per row per bin, B-row sub-group width.
+// lanes per row and lanes per A entry, per bin.
 struct BinPlan {
   bool known = false;
   int count[kNB] = {0};
   int lanes[kNB] = {0};
-  int sub = 16;
+  int sub[kNB] = {0};       // lanes sharing one A entry's B row, per bin
   int maxbin = kMaxLdsBin;  // last LDS bin; bins above go to the heavy kernel
   int heavy_slots = 1;
   int n = 0;
@@ -57,5 +58,25 @@ hipError_t launch_numeric(const Problem *dpr, const BinPlan &bp, const WsLayout 
                           const int32_t *crp, int32_t *ccol, void *cval, int dtype,
                           hipStream_t st);
 hipError_t configure_lds_limits(size_t lds_max);
+
+hipError_t launch_backward(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
+                           const int32_t *crp, const int32_t *ccol, const void *w, void *dA,
+                           int64_t nnzA, void *dB, int64_t nnzB, int dtype, hipStream_t st);
+hipError_t configure_backward_lds(size_t lds_max);
+
+hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
+                      int r, float prune, int topk, int cap, int32_t *pcol, float *pval,
+                      int32_t *ycnt, hipStream_t st);
+hipError_t launch_mcl_compact(int n, int cap, const int32_t *yrp, const int32_t *pcol,
+                              const float *pval, int32_t *ycol, float *yval, const WsHeader *hdr,
+                              hipStream_t st);
+hipError_t configure_mcl_lds(size_t lds_max);
+size_t mcl_lds_bytes(int b, int G);
+int num_table_slots(int b, int G);
+
+// LDS bytes of one block of the symbolic / numeric kernel of bin b with G
+// lanes per row.
+size_t sym_lds_bytes(int b, int G);
+size_t num_lds_bytes(int b, int G, size_t vbytes, bool pack);
 
 }  // namespace spg

@@ -1,0 +1,659 @@
+// Row kernels of the local product C = sum_k A_k B_k (K = 1: C = A B, paper
+// §2): symbolic count (a3) and numeric pass (a5) per row bin, the sort-based
+// fallback and the heavy-row kernels, with their launchers.
+//
+// Rows of one bin are processed by groups of G lanes; groups of at most 64
+// lanes share a block of 256 threads (several rows per block), larger
+// groups are a block of their own.  Every kernel loops over its row list
+// grid-stride style and reads the list length from the workspace header,
+// so the same launch is valid eagerly (exact grid) and inside a graph
+// (persistent grid).
+#include <vector>
+
+#include "internal.hpp"
+#include "rowops.hpp"
+
+namespace spg {
+
+constexpr int kUnroll = 4;  // entries per lane in flight
+
+// Geometry of a row group of G lanes: groups of at most 64 lanes share a
+// 256-thread block (R rows per block, each wave's groups independent);
+// larger groups are the block.
+template <int G>
+struct Geom {
+  static constexpr bool BLOCK = G > kWave;
+  static constexpr int WG = BLOCK ? G : 256;
+  static constexpr int R = WG / G;
+};
+
+// Row index held by a group; for groups of a whole wave or more it is
+// wave-uniform and is moved to a scalar register.
+template <int G>
+__device__ __forceinline__ int uniform_if_wave(int v) {
+  return G >= kWave ? __builtin_amdgcn_readfirstlane(v) : v;
+}
+
+// ---------------------------------------------------------------------------
+// a3: exact distinct-column count of each row with an LDS hash set.
+template <int G>
+__global__ __launch_bounds__(Geom<G>::WG) void k_sym_rows(const Problem *__restrict__ pr,
+                                                          const int32_t *__restrict__ rows,
+                                                          const WsHeader *__restrict__ hdr,
+                                                          int bin, int lS, int log2T,
+                                                          int32_t *__restrict__ cnt) {
+  using GM = Geom<G>;
+  extern __shared__ __align__(16) int smem[];
+  const int T = 1 << log2T;
+  const int rslot = threadIdx.x / G, l = threadIdx.x % G;
+  int *tab = smem + rslot * T;
+  int *sb = smem + GM::R * T + rslot * G;
+  int *sl = smem + GM::R * T + GM::R * G + rslot * G;
+  int *rowcnt = smem + GM::R * T + 2 * GM::R * G + rslot;
+  if (hdr->status) return;
+  const int count = hdr->bin_count[bin];
+  const int start = hdr->bin_start[bin];
+  Stage<float> st{sb, sl, nullptr};
+  for (int ri = blockIdx.x * GM::R + rslot; ri < count; ri += gridDim.x * GM::R) {
+    const int i = uniform_if_wave<G>(rows[start + ri]);
+    int4 *t4 = reinterpret_cast<int4 *>(tab);
+    for (int s = l; s < T / 4; s += G) t4[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+    if (l == 0) *rowcnt = 0;
+    group_sync<GM::BLOCK>();
+    int mine = 0;
+    for_each_product<GM::BLOCK, false, G, kUnroll, float>(
+        pr, i, true, l, lS, st, [&](int col, float) {
+          uint32_t h = scramble_slot((uint32_t)col, log2T);
+          while (true) {
+            const int old = atomicCAS(&tab[h], kEmpty, col);
+            if (old == kEmpty) { ++mine; break; }
+            if (old == col) break;
+            h = (h + 1) & (T - 1);
+          }
+        });
+    if (mine) atomicAdd(rowcnt, mine);
+    group_sync<GM::BLOCK>();
+    if (l == 0) cnt[i] = *rowcnt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a5: numeric pass with an order-preserving home slot.
+//
+// The home slot floor(col * T / n) never decreases with col and linear
+// probing only walks forward, so a key x that ends up after a larger key y
+// always has y inside its own probe path [home(x), slot(x)): those are the
+// only out-of-order pairs, and every slot on that path was filled before x
+// arrived.  So when x is inserted fresh at displacement d > 0 it walks its
+// path once, adds one to the counter of each larger key it passed and
+// subtracts their number from its own: the final rank of a key is
+// (occupied slots before it) + (its counter).  The output pass gives each
+// lane a contiguous, odd-length chunk of slots (no LDS bank conflicts), one
+// group scan turns its occupied count into a base rank, and the lane writes
+// its entries straight to their place in the output row.  A probe longer
+// than `maxwin` hands the row to the sort-based fallback kernel.
+//
+// PACK (n <= 2^24): the counter lives in the top byte of the key word
+// (biased by 128; it stays within [-2*kTail, 2*kTail]), so the table is one
+// int array plus the values.
+template <bool PACK>
+struct KeyCode {
+  __device__ static int make(int col) { return PACK ? (int)((uint32_t)col | 0x80000000u) : col; }
+  __device__ static int col(int w) { return PACK ? (int)((uint32_t)w & 0xffffffu) : w; }
+  __device__ static int adj(int w) { return PACK ? (int)((uint32_t)w >> 24) - 128 : 0; }
+};
+
+template <int G, typename VT, bool PACK>
+__global__ __launch_bounds__(Geom<G>::WG) void k_num_rows(const Problem *__restrict__ pr,
+                                                          const int32_t *__restrict__ rows,
+                                                          WsHeader *__restrict__ hdr, int bin,
+                                                          int lS, int TT, uint32_t mul,
+                                                          int maxwin,
+                                                          const int32_t *__restrict__ crp,
+                                                          int32_t *__restrict__ ccol,
+                                                          VT *__restrict__ cval,
+                                                          int32_t *__restrict__ fb_rows) {
+  using GM = Geom<G>;
+  using KC = KeyCode<PACK>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int rslot = threadIdx.x / G, l = threadIdx.x % G;
+  VT *vals_all = reinterpret_cast<VT *>(smem_raw);
+  VT *sa_all = vals_all + (size_t)GM::R * TT;
+  int *keys_all = reinterpret_cast<int *>(sa_all + (size_t)GM::R * G);
+  int *adj_all = keys_all + (size_t)GM::R * TT;
+  int *sb_all = adj_all + (PACK ? 0 : (size_t)GM::R * TT);
+  int *sl_all = sb_all + (size_t)GM::R * G;
+  int *rowflag = sl_all + (size_t)GM::R * G;
+  int *wtot = rowflag + GM::R;
+  VT *val = vals_all + (size_t)rslot * TT;
+  int *key = keys_all + (size_t)rslot * TT;
+  int *adj = adj_all + (size_t)rslot * TT;
+  Stage<VT> st{sb_all + rslot * G, sl_all + rslot * G, sa_all + rslot * G};
+  if (hdr->status) return;
+  const int count = hdr->bin_count[bin];
+  const int start = hdr->bin_start[bin];
+  const int c = TT / G;  // slots per lane in the output pass (odd)
+  for (int ri = blockIdx.x * GM::R + rslot; ri < count; ri += gridDim.x * GM::R) {
+    const int i = uniform_if_wave<G>(rows[start + ri]);
+    {
+      int4 *k4 = reinterpret_cast<int4 *>(key);
+      for (int s = l; s < TT / 4; s += G) k4[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+      if (!PACK) {
+        int4 *a4 = reinterpret_cast<int4 *>(adj);
+        for (int s = l; s < TT / 4; s += G) a4[s] = make_int4(0, 0, 0, 0);
+      }
+      for (int s = l; s < TT; s += G) val[s] = VT(0);
+    }
+    if (l == 0) rowflag[rslot] = 0;
+    group_sync<GM::BLOCK>();
+    for_each_product<GM::BLOCK, true, G, kUnroll, VT>(
+        pr, i, true, l, lS, st, [&](int col, VT v) {
+          int h = (int)mono_slot((uint32_t)col, mul);
+          int d = 0;
+          int old = atomicCAS(&key[h], kEmpty, KC::make(col));
+          while (old != kEmpty && KC::col(old) != col) {
+            if (d == maxwin) {  // long probe: the fallback redoes this row
+              rowflag[rslot] = 1;
+              return;
+            }
+            ++d;
+            ++h;  // h <= home + maxwin < TT
+            old = atomicCAS(&key[h], kEmpty, KC::make(col));
+          }
+          lds_add(&val[h], v);
+          if (old == kEmpty && d > 0) {
+            int larger = 0;
+            for (int t = h - d; t < h; ++t) {
+              if (KC::col(key[t]) > col) {
+                if (PACK) atomicAdd(&key[t], 1 << 24);
+                else atomicAdd(&adj[t], 1);
+                ++larger;
+              }
+            }
+            if (larger) {
+              if (PACK) atomicSub(&key[h], larger << 24);
+              else atomicSub(&adj[h], larger);
+            }
+          }
+        });
+    group_sync<GM::BLOCK>();
+    const bool ok = rowflag[rslot] == 0;
+    const int rs = crp[i];
+    const int nnz = crp[i + 1] - rs;
+    const int s0 = l * c;
+    int mine = 0;
+    for (int j = 0; j < c; ++j) mine += key[s0 + j] != kEmpty;
+    int total;
+    int r = group_excl_scan<GM::BLOCK, G>(mine, l, wtot, total);
+    if (ok && nnz > 0) {
+      SPG_GLOBAL int32_t *cb = gpw(ccol) + rs;
+      SPG_GLOBAL VT *vb = gpw(cval) + rs;
+      for (int j = 0; j < c; ++j) {
+        const int w = key[s0 + j];
+        if (w != kEmpty) {
+          int rr = r + (PACK ? KC::adj(w) : adj[s0 + j]);
+          rr = rr < 0 ? 0 : (rr >= nnz ? nnz - 1 : rr);  // in bounds even for a changed pattern
+          cb[(uint32_t)rr] = KC::col(w);
+          vb[(uint32_t)rr] = val[s0 + j];
+          ++r;
+        }
+      }
+    }
+    if (ok && l == 0 && total != nnz) atomicOr(&hdr->status, kStatInvalid);
+    if (l == 0 && !ok) {
+      const int slot = atomicAdd(&hdr->fallback_count, 1);
+      fb_rows[slot] = i;
+    }
+    group_sync<GM::BLOCK>();
+  }
+}
+
+// Fallback numeric pass: scrambled LDS hash, in-place compaction, bitonic
+// sort of (column, value) pairs, coalesced write.  One row per block.
+template <typename VT>
+__global__ __launch_bounds__(1024) void k_num_fallback(const Problem *__restrict__ pr,
+                                                       const int32_t *__restrict__ fb_rows,
+                                                       WsHeader *__restrict__ hdr, int TF,
+                                                       int lS, const int32_t *__restrict__ crp,
+                                                       int32_t *__restrict__ ccol,
+                                                       VT *__restrict__ cval) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int wtot[16];
+  VT *val = reinterpret_cast<VT *>(smem_raw);
+  VT *sa = val + TF;
+  int *key = reinterpret_cast<int *>(sa + 1024);
+  int *sb = key + TF;
+  int *sl = sb + 1024;
+  if (hdr->status) return;
+  const int count = hdr->fallback_count;
+  const int tid = threadIdx.x;
+  Stage<VT> st{sb, sl, sa};
+  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+    const int i = fb_rows[ri];
+    const int rs = crp[i];
+    const int nnz = crp[i + 1] - rs;
+    int P2 = 1;
+    while (P2 < nnz) P2 <<= 1;
+    int T = 2 * P2;
+    if (T > TF) T = TF;
+    int log2T = 0;
+    while ((1 << log2T) < T) ++log2T;
+    for (int s = tid; s < T; s += 1024) {
+      key[s] = kEmpty;
+      val[s] = VT(0);
+    }
+    __syncthreads();
+    for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, [&](int col, VT v) {
+      uint32_t h = scramble_slot((uint32_t)col, log2T);
+      for (int probes = 0;; ++probes) {
+        const int old = atomicCAS(&key[h], kEmpty, col);
+        if (old == kEmpty || old == col) {
+          lds_add(&val[h], v);
+          break;
+        }
+        if (probes >= T) {  // more distinct columns than the symbolic pass counted
+          atomicOr(&hdr->status, kStatInvalid);
+          break;
+        }
+        h = (h + 1) & (T - 1);
+      }
+    });
+    __syncthreads();
+    // in-place compaction in slot order (a round's reads precede its writes)
+    int pre = 0;
+    for (int s0 = 0; s0 < T; s0 += 1024) {
+      const int s = s0 + tid;
+      const int x = s < T ? key[s] : kEmpty;
+      const VT v = s < T ? val[s] : VT(0);
+      int tot;
+      const int pos = pre + group_excl_scan<true, 1024>(x != kEmpty ? 1 : 0, tid, wtot, tot);
+      if (x != kEmpty) {
+        key[pos] = x;
+        val[pos] = v;
+      }
+      pre += tot;
+      __syncthreads();
+    }
+    if (tid == 0 && pre != nnz) atomicOr(&hdr->status, kStatInvalid);
+    for (int s = nnz + tid; s < P2; s += 1024) key[s] = 0x7fffffff;
+    __syncthreads();
+    for (int kk = 2; kk <= P2; kk <<= 1) {
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int t = tid; t < P2 / 2; t += 1024) {
+          const int a = 2 * j * (t / j) + (t % j);
+          const int b = a + j;
+          const bool up = (a & kk) == 0;
+          const int ka = key[a], kb = key[b];
+          if ((ka > kb) == up) {
+            key[a] = kb;
+            key[b] = ka;
+            const VT va = val[a];
+            val[a] = val[b];
+            val[b] = va;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int t = tid; t < nnz; t += 1024) {
+      ccol[rs + t] = key[t];
+      cval[rs + t] = val[t];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Heavy rows (beyond every LDS table): a column bitmap (LDS when it fits,
+// else the slot's global bitmap), one block of 1024 threads per row; block b
+// owns slot b of the heavy scratch.
+
+template <bool LDSMAP>
+__global__ __launch_bounds__(1024) void k_sym_heavy(const Problem *__restrict__ pr,
+                                                    const int32_t *__restrict__ rows,
+                                                    const WsHeader *__restrict__ hdr, int blo,
+                                                    int lS, uint32_t *gbitmap, int32_t *cnt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sb[1024], sl[1024];
+  __shared__ int total;
+  const int n = pr->n;
+  const int nw = (n + 31) >> 5;
+  uint32_t *map = LDSMAP ? reinterpret_cast<uint32_t *>(smem_raw) : gbitmap + (size_t)blockIdx.x * nw;
+  if (hdr->status) return;
+  const int start = hdr->bin_start[blo];
+  const int count = hdr->bin_start[kHeavyBin + 1] - start;
+  const int tid = threadIdx.x;
+  Stage<float> st{sb, sl, nullptr};
+  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+    const int i = rows[start + ri];
+    for (int w = tid; w < nw; w += 1024) map[w] = 0u;
+    if (tid == 0) total = 0;
+    if (!LDSMAP) __threadfence();
+    __syncthreads();
+    int mine = 0;
+    for_each_product<true, false, 1024, kUnroll, float>(pr, i, true, tid, lS, st,
+                                                        [&](int col, float) {
+      const uint32_t bit = 1u << (col & 31);
+      const uint32_t old = atomicOr(&map[col >> 5], bit);
+      mine += (old & bit) ? 0 : 1;
+    });
+    if (mine) atomicAdd(&total, mine);
+    __syncthreads();
+    if (tid == 0) cnt[i] = total;
+    __syncthreads();
+  }
+}
+
+// Numeric pass of heavy rows with the slot's dense accumulator in global
+// memory.  Pass 1 marks columns and zeroes the accumulator entries it marks
+// first, pass 2 adds the products, pass 3 walks the bitmap in column order,
+// so the output row comes out sorted.
+template <bool LDSMAP, typename VT>
+__global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ pr,
+                                                    const int32_t *__restrict__ rows,
+                                                    WsHeader *__restrict__ hdr, int blo, int lS,
+                                                    uint32_t *gbitmap, VT *gacc,
+                                                    const int32_t *__restrict__ crp,
+                                                    int32_t *__restrict__ ccol,
+                                                    VT *__restrict__ cval) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int wtot[16];
+  __shared__ int sb[1024], sl[1024];
+  __shared__ VT sa[1024];
+  const int n = pr->n;
+  const int nw = (n + 31) >> 5;
+  uint32_t *map = LDSMAP ? reinterpret_cast<uint32_t *>(smem_raw) : gbitmap + (size_t)blockIdx.x * nw;
+  VT *acc = gacc + (size_t)blockIdx.x * n;
+  if (hdr->status) return;
+  const int start = hdr->bin_start[blo];
+  const int count = hdr->bin_start[kHeavyBin + 1] - start;
+  const int tid = threadIdx.x;
+  Stage<VT> st{sb, sl, sa};
+  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+    const int i = rows[start + ri];
+    for (int w = tid; w < nw; w += 1024) map[w] = 0u;
+    __threadfence();
+    __syncthreads();
+    for_each_product<true, false, 1024, kUnroll, VT>(pr, i, true, tid, lS, st,
+                                                     [&](int col, VT) {
+      const uint32_t bit = 1u << (col & 31);
+      const uint32_t old = atomicOr(&map[col >> 5], bit);
+      if (!(old & bit)) acc[col] = VT(0);
+    });
+    // the accumulator lives in global memory: complete this pass's stores
+    // at device scope and drop stale L1 lines before the next pass
+    __threadfence();
+    __syncthreads();
+    for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st,
+                                                    [&](int col, VT v) { global_add(&acc[col], v); });
+    __threadfence();
+    __syncthreads();
+    const int rs = crp[i];
+    const int re = crp[i + 1];
+    int pre = 0;
+    for (int w0 = 0; w0 < nw; w0 += 1024) {
+      const int w = w0 + tid;
+      const uint32_t bits = w < nw ? map[w] : 0u;
+      int tot;
+      int o = rs + pre + group_excl_scan<true, 1024>(__popc(bits), tid, wtot, tot);
+      uint32_t b = bits;
+      while (b) {
+        const int j = __ffs(b) - 1;
+        b &= b - 1;
+        const int col = (w << 5) + j;
+        if (o < re) {  // the symbolic count bounds the row (a changed pattern is flagged)
+          ccol[o] = col;
+          cval[o] = acc[col];
+        }
+        ++o;
+      }
+      pre += tot;
+    }
+    if (tid == 0 && pre != re - rs) atomicOr(&hdr->status, kStatInvalid);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+static int blocks_per_cu(size_t lds, int wg, size_t lds_limit_cu) {
+  int by_lds = lds ? (int)(lds_limit_cu / lds) : 64;
+  int by_thr = 2048 / wg;
+  int b = by_lds < by_thr ? by_lds : by_thr;
+  return b < 1 ? 1 : b;
+}
+
+static int wg_for(int G) { return G <= kWave ? 256 : G; }
+
+static int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// A heavy row's column bitmap lives in LDS when it fits one block.
+static bool lds_bitmap_fits(int n, size_t extra) {
+  return n <= kLdsBitmapCols &&
+         (size_t)((n + 31) >> 5) * 4 + extra + 1024 <= dev_info().lds_per_block;
+}
+
+static int bins_count(const BinPlan &bp, int lo, int hi) {
+  if (!bp.known) return -1;
+  int c = 0;
+  for (int b = lo; b <= hi; ++b) c += bp.count[b];
+  return c;
+}
+
+static int grid_for(int count, int rows_per_block, int cap) {
+  if (count < 0) return cap;
+  const int need = (count + rows_per_block - 1) / rows_per_block;
+  return need < cap ? need : cap;
+}
+
+// B-row lanes per entry, never more than the group.
+static int sub_log2(const BinPlan &bp, int b, int G) {
+  int S = bp.sub[b] > 0 ? bp.sub[b] : 16;
+  if (S > G) S = G;
+  return log2i(S);
+}
+
+size_t sym_lds_bytes(int b, int G) {
+  const int WG = wg_for(G), R = WG / G;
+  return (size_t)R * bin_slots(b) * 4 + (size_t)2 * R * G * 4 + (size_t)R * 4 + 64;
+}
+
+// Table slots of a numeric row: T + at least kTail, as G lanes times an odd
+// chunk length (the output pass reads chunks without LDS bank conflicts).
+int num_table_slots(int b, int G) {
+  int c = (bin_slots(b) + kTail + G - 1) / G;
+  if (!(c & 1)) ++c;
+  return c * G;
+}
+
+size_t num_lds_bytes(int b, int G, size_t vbytes, bool pack) {
+  const int WG = wg_for(G), R = WG / G;
+  const size_t TT = (size_t)num_table_slots(b, G);
+  return (size_t)R * TT * (vbytes + (pack ? 4 : 8)) + (size_t)R * G * (vbytes + 8) +
+         (size_t)R * 4 + 64;
+}
+
+template <int G>
+static void sym_launch(const Problem *dpr, const int32_t *rows, const WsHeader *hdr, int bin,
+                       int lS, int log2T, int32_t *cnt, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(k_sym_rows<G>, dim3(grid), dim3(Geom<G>::WG), lds, st, dpr, rows, hdr, bin,
+                     lS, log2T, cnt);
+}
+
+hipError_t launch_symbolic_bins(const Problem *dpr, const BinPlan &bp, const WsLayout &L,
+                                char *ws, int32_t *cnt, hipStream_t st) {
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  const int32_t *rows = reinterpret_cast<const int32_t *>(ws + L.rows);
+  const DevInfo &D = dev_info();
+  for (int b = 1; b <= bp.maxbin; ++b) {
+    if (bp.known && bp.count[b] == 0) continue;
+    int G = bp.lanes[b];
+    while (G < 1024 && sym_lds_bytes(b, G) > D.lds_per_block) G *= 2;  // fewer rows per block
+    const int WG = wg_for(G);
+    const int R = WG / G;
+    const size_t lds = sym_lds_bytes(b, G);
+    const int grid = grid_for(bins_count(bp, b, b), R, D.cus * blocks_per_cu(lds, WG, D.lds_per_cu));
+    const int lt = log2i(bin_slots(b));
+    const int lS = sub_log2(bp, b, G);
+    switch (G) {
+      case 8: sym_launch<8>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
+      case 16: sym_launch<16>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
+      case 32: sym_launch<32>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
+      case 64: sym_launch<64>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
+      case 128: sym_launch<128>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
+      case 256: sym_launch<256>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
+      case 512: sym_launch<512>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
+      default: sym_launch<1024>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
+    }
+  }
+  const int hc = bins_count(bp, bp.maxbin + 1, kHeavyBin);
+  if (hc != 0) {
+    const int grid = grid_for(hc, 1, bp.heavy_slots);
+    const int lS = sub_log2(bp, kHeavyBin, 1024);
+    if (lds_bitmap_fits(bp.n, 9 * 1024)) {
+      const size_t lds = (size_t)((bp.n + 31) >> 5) * 4;
+      hipLaunchKernelGGL(k_sym_heavy<true>, dim3(grid), dim3(1024), lds, st, dpr, rows, hdr,
+                         bp.maxbin + 1, lS, (uint32_t *)nullptr, cnt);
+    } else {
+      hipLaunchKernelGGL(k_sym_heavy<false>, dim3(grid), dim3(1024), 0, st, dpr, rows, hdr,
+                         bp.maxbin + 1, lS, reinterpret_cast<uint32_t *>(ws + L.heavymap), cnt);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <int G, typename VT, bool PACK>
+static void num_launch(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin, int lS,
+                       int TT, uint32_t mul, int maxwin, const int32_t *crp, int32_t *ccol,
+                       VT *cval, int32_t *fb, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_num_rows<G, VT, PACK>), dim3(grid), dim3(Geom<G>::WG), lds, st, dpr,
+                     rows, hdr, bin, lS, TT, mul, maxwin, crp, ccol, cval, fb);
+}
+
+template <typename VT, bool PACK>
+static void num_launch_g(int G, const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin,
+                         int lS, int TT, uint32_t mul, int maxwin, const int32_t *crp,
+                         int32_t *ccol, VT *cval, int32_t *fb, int grid, size_t lds,
+                         hipStream_t st) {
+  switch (G) {
+#define SPG_NUM_CASE(g) \
+  case g: num_launch<g, VT, PACK>(dpr, rows, hdr, bin, lS, TT, mul, maxwin, crp, ccol, cval, fb, grid, lds, st); break;
+    SPG_NUM_CASE(8)
+    SPG_NUM_CASE(16)
+    SPG_NUM_CASE(32)
+    SPG_NUM_CASE(64)
+    SPG_NUM_CASE(128)
+    SPG_NUM_CASE(256)
+    SPG_NUM_CASE(512)
+    default: num_launch<1024, VT, PACK>(dpr, rows, hdr, bin, lS, TT, mul, maxwin, crp, ccol, cval, fb, grid, lds, st);
+#undef SPG_NUM_CASE
+  }
+}
+
+template <typename VT>
+static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLayout &L,
+                               char *ws, const int32_t *crp, int32_t *ccol, VT *cval,
+                               hipStream_t st) {
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  const int32_t *rows = reinterpret_cast<const int32_t *>(ws + L.rows);
+  int32_t *fb = reinterpret_cast<int32_t *>(ws + L.fbrows);
+  const DevInfo &D = dev_info();
+  const int maxwin = bp.maxwin < kTail ? bp.maxwin : kTail;
+  const bool pack = bp.n <= (1 << 24);
+  for (int b = 1; b <= bp.maxbin; ++b) {
+    if (bp.known && bp.count[b] == 0) continue;
+    int G = bp.lanes[b];
+    while (G < 1024 && num_lds_bytes(b, G, sizeof(VT), pack) > D.lds_per_block) G *= 2;
+    const int WG = wg_for(G);
+    const int R = WG / G;
+    const int T = bin_slots(b);
+    const int TT = num_table_slots(b, G);
+    const size_t lds = num_lds_bytes(b, G, sizeof(VT), pack);
+    const int grid = grid_for(bins_count(bp, b, b), R, D.cus * blocks_per_cu(lds, WG, D.lds_per_cu));
+    const uint32_t mul = mono_mul(T, bp.n);
+    const int lS = sub_log2(bp, b, G);
+    if (pack)
+      num_launch_g<VT, true>(G, dpr, rows, hdr, b, lS, TT, mul, maxwin, crp, ccol, cval, fb, grid, lds, st);
+    else
+      num_launch_g<VT, false>(G, dpr, rows, hdr, b, lS, TT, mul, maxwin, crp, ccol, cval, fb, grid, lds, st);
+  }
+  if (bins_count(bp, 1, bp.maxbin) != 0) {
+    // rows the LDS kernels hand over (probe longer than the window)
+    const int TF = bin_slots(bp.maxbin);
+    const size_t lds = (size_t)TF * (sizeof(VT) + 4) + (size_t)1024 * (sizeof(VT) + 8);
+    hipLaunchKernelGGL(k_num_fallback<VT>, dim3(D.cus), dim3(1024), lds, st, dpr, fb, hdr, TF,
+                       sub_log2(bp, bp.maxbin, 1024), crp, ccol, cval);
+  }
+  const int hc = bins_count(bp, bp.maxbin + 1, kHeavyBin);
+  if (hc != 0) {
+    const int grid = grid_for(hc, 1, bp.heavy_slots);
+    VT *acc = reinterpret_cast<VT *>(ws + L.heavyacc);
+    const int lS = sub_log2(bp, kHeavyBin, 1024);
+    if (lds_bitmap_fits(bp.n, 8 * 1024 + 1024 * sizeof(VT))) {
+      const size_t lds = (size_t)((bp.n + 31) >> 5) * 4;
+      hipLaunchKernelGGL((k_num_heavy<true, VT>), dim3(grid), dim3(1024), lds, st, dpr, rows,
+                         hdr, bp.maxbin + 1, lS, (uint32_t *)nullptr, acc, crp, ccol, cval);
+    } else {
+      hipLaunchKernelGGL((k_num_heavy<false, VT>), dim3(grid), dim3(1024), 0, st, dpr, rows, hdr,
+                         bp.maxbin + 1, lS, reinterpret_cast<uint32_t *>(ws + L.heavymap), acc,
+                         crp, ccol, cval);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_numeric(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
+                          const int32_t *crp, int32_t *ccol, void *cval, int dtype,
+                          hipStream_t st) {
+  if (dtype == SPG_F64)
+    return numeric_impl<double>(dpr, bp, L, ws, crp, ccol, static_cast<double *>(cval), st);
+  return numeric_impl<float>(dpr, bp, L, ws, crp, ccol, static_cast<float *>(cval), st);
+}
+
+// Kernels that may use more than 64 KiB of dynamic LDS are opted in once.
+template <typename VT, bool PACK>
+static void num_kernels(std::vector<const void *> &ks) {
+  ks.push_back(reinterpret_cast<const void *>(&k_num_rows<8, VT, PACK>));
+  ks.push_back(reinterpret_cast<const void *>(&k_num_rows<16, VT, PACK>));
+  ks.push_back(reinterpret_cast<const void *>(&k_num_rows<32, VT, PACK>));
+  ks.push_back(reinterpret_cast<const void *>(&k_num_rows<64, VT, PACK>));
+  ks.push_back(reinterpret_cast<const void *>(&k_num_rows<128, VT, PACK>));
+  ks.push_back(reinterpret_cast<const void *>(&k_num_rows<256, VT, PACK>));
+  ks.push_back(reinterpret_cast<const void *>(&k_num_rows<512, VT, PACK>));
+  ks.push_back(reinterpret_cast<const void *>(&k_num_rows<1024, VT, PACK>));
+}
+
+hipError_t configure_lds_limits(size_t lds_max) {
+  std::vector<const void *> ks = {
+      reinterpret_cast<const void *>(&k_sym_rows<8>),
+      reinterpret_cast<const void *>(&k_sym_rows<16>),
+      reinterpret_cast<const void *>(&k_sym_rows<32>),
+      reinterpret_cast<const void *>(&k_sym_rows<64>),
+      reinterpret_cast<const void *>(&k_sym_rows<128>),
+      reinterpret_cast<const void *>(&k_sym_rows<256>),
+      reinterpret_cast<const void *>(&k_sym_rows<512>),
+      reinterpret_cast<const void *>(&k_sym_rows<1024>),
+      reinterpret_cast<const void *>(&k_sym_heavy<true>),
+      reinterpret_cast<const void *>(&k_num_fallback<float>),
+      reinterpret_cast<const void *>(&k_num_fallback<double>),
+      reinterpret_cast<const void *>(&k_num_heavy<true, float>),
+      reinterpret_cast<const void *>(&k_num_heavy<true, double>),
+  };
+  num_kernels<float, true>(ks);
+  num_kernels<float, false>(ks);
+  num_kernels<double, true>(ks);
+  num_kernels<double, false>(ks);
+  for (const void *k : ks) {
+    hipError_t e =
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace spg

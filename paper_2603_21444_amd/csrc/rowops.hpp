@@ -1,0 +1,192 @@
+// Row-level building blocks shared by the row kernels: group
+// synchronisation and scans, and the enumeration of every scalar product
+// a_ik * b_kj that lands in row i of C = sum_k A_k B_k.
+#pragma once
+
+#include "common.hpp"
+
+namespace spg {
+
+// A "group" is the set of lanes working on one row.  Groups of at most 64
+// lanes sit inside one wave (lanes [g0, g0+G)) and run independently of the
+// wave's other groups; larger groups are a whole block.  group_sync orders
+// the group's LDS accesses.
+template <bool BLOCK>
+__device__ __forceinline__ void group_sync() {
+  if (BLOCK) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+}
+
+// Exclusive prefix sum of v over the group's lanes (l = lane in group);
+// `total` gets the group sum.  BLOCK groups use wtot[blockDim/64] in LDS.
+template <bool BLOCK, int G>
+__device__ __forceinline__ int group_excl_scan(int v, int l, int *wtot, int &total) {
+  int x = v;
+  if (!BLOCK) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+      const int y = __shfl_up(x, off, G);
+      if (l >= off) x += y;
+    }
+    total = __shfl(x, G - 1, G);
+    return x - v;
+  }
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane_id() >= off) x += y;
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) wtot[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int ww = 0; ww < G / kWave; ++ww) {
+    const int c = wtot[ww];
+    pre += (ww < w) ? c : 0;
+    tot += c;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+// Group-wide sum / max.  BLOCK groups reduce through red[blockDim/64].
+template <bool BLOCK, int G, typename T>
+__device__ __forceinline__ T group_sum(T v, T *red) {
+  if (!BLOCK) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  T t = T(0);
+#pragma unroll
+  for (int w = 0; w < G / kWave; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+template <bool BLOCK, int G>
+__device__ __forceinline__ unsigned long long group_max_u64(unsigned long long v,
+                                                           unsigned long long *red) {
+  if (!BLOCK) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(v, off, G);
+      v = o > v ? o : v;
+    }
+    return v;
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+#pragma unroll
+  for (int w = 0; w < G / kWave; ++w) t = red[w] > t ? red[w] : t;
+  __syncthreads();
+  return t;
+}
+
+// Staging area of one group in LDS: one A entry per lane of a chunk.
+template <typename VT>
+struct Stage {
+  int *b0;   // start of the B row in bcol/bval
+  int *len;  // length of the B row
+  VT *a;     // value a_ik
+};
+
+// Calls f(col, a_ik * b_kj) for every product of row i.  The entries of an
+// A row are taken in chunks of G: lane l stages entry c0+l in LDS (one
+// coalesced read of A, one gather of B row bounds).  Then S = 2^lS lanes
+// share each entry: lane l reads position (l mod S) of the B rows of
+// entries l/S, l/S + G/S, ..., U entries at a time so that U loads are in
+// flight together, and consecutive lanes read consecutive B entries.
+// Positions beyond S (B rows longer than S) follow in a second loop.
+template <bool BLOCK, bool VALUES, int G, int U, typename VT, typename F>
+__device__ __forceinline__ void for_each_product(const Problem *__restrict__ pr, int i,
+                                                 bool active, int l, int lS, Stage<VT> st,
+                                                 F &&f) {
+  const int K = pr->K;
+  const int S = 1 << lS;
+  const int ES = G >> lS;
+  const int sg = l >> lS;
+  const int q0 = l & (S - 1);
+  for (int k = 0; k < K; ++k) {
+    const Part &P = pr->part[k];
+    const SPG_GLOBAL int32_t *brp = gp(P.brp);
+    const SPG_GLOBAL int32_t *bcol = gp(P.bcol);
+    const SPG_GLOBAL VT *bval = gp(static_cast<const VT *>(P.bval));
+    int as = 0, ae = 0;
+    if (active) a_row(P, i, as, ae);
+    const int nA = ae - as;
+    for (int c0 = 0; c0 < nA; c0 += G) {
+      const int e = c0 + l;
+      if (e < nA) {
+        int r;
+        VT a = VT(1);
+        if (P.a_identity) {
+          r = i;
+        } else {
+          r = gp(P.acol)[as + e];
+          if (VALUES) a = gp(static_cast<const VT *>(P.aval))[as + e];
+        }
+        const int b0 = brp[r];
+        st.b0[l] = b0;
+        st.len[l] = brp[r + 1] - b0;
+        if (VALUES) st.a[l] = a;
+      }
+      const int nE = min(G, nA - c0);
+      group_sync<BLOCK>();
+      for (int t0 = sg; t0 < nE; t0 += ES * U) {
+        int col[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int ee = t0 + ES * u;
+          col[u] = -1;
+          v[u] = VT(0);
+          if (ee < nE && q0 < st.len[ee]) {
+            const int idx = st.b0[ee] + q0;
+            col[u] = bcol[idx];
+            if (VALUES) v[u] = st.a[ee] * bval[idx];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (col[u] >= 0) f(col[u], v[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int ee = t0 + ES * u;
+          if (ee < nE) {
+            const int len = st.len[ee];
+            for (int q = q0 + S; q < len; q += S) {
+              const int idx = st.b0[ee] + q;
+              f(bcol[idx], VALUES ? st.a[ee] * bval[idx] : VT(0));
+            }
+          }
+        }
+      }
+      group_sync<BLOCK>();
+    }
+  }
+}
+
+}  // namespace spg

@@ -95,12 +95,22 @@ def _distinct_rows(rng, m: int, n: int, d: int) -> np.ndarray:
     if 4 * d > n:  # dense-ish: per-row permutation prefix
         return np.stack([rng.permutation(n)[:d] for _ in range(m)]).astype(np.int64)
     cols = rng.integers(0, n, size=(m, d), dtype=np.int64)
-    while True:
-        s = np.sort(cols, axis=1)
-        bad = np.nonzero((s[:, 1:] == s[:, :-1]).any(axis=1))[0]
-        if bad.size == 0:
-            return cols
-        cols[bad] = rng.integers(0, n, size=(bad.size, d), dtype=np.int64)
+    s = np.sort(cols, axis=1)
+    bad = np.nonzero((s[:, 1:] == s[:, :-1]).any(axis=1))[0]
+    for i in bad:  # keep the first copy of each column, redraw the repeats
+        row = cols[i]
+        _, first = np.unique(row, return_index=True)
+        keep = np.zeros(d, dtype=bool)
+        keep[first] = True
+        have = set(row[keep].tolist())
+        for p in np.nonzero(~keep)[0]:
+            while True:
+                c = int(rng.integers(0, n))
+                if c not in have:
+                    have.add(c)
+                    row[p] = c
+                    break
+    return cols
 
 
 def _csr_from_rows(m, n, cols_md, lens, vals_rng, values, dtype, sort_rows):

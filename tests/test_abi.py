@@ -49,7 +49,10 @@ def test_tuning_roundtrip_and_rejection():
     assert L.spgemm_plan_create(0, C.byref(p)) == 0
     t = binding.default_tuning()
     assert L.spgemm_plan_set_tuning(p, C.byref(t)) == 0
-    t.sub = 3
+    t.lanes[3] = 3
+    assert L.spgemm_plan_set_tuning(p, C.byref(t)) == binding.SPG_ERR_ARG
+    t = binding.default_tuning()
+    t.max_window = 0
     assert L.spgemm_plan_set_tuning(p, C.byref(t)) == binding.SPG_ERR_ARG
     L.spgemm_plan_destroy(p)
     assert L.spgemm_plan_create(0, None) == binding.SPG_ERR_ARG

@@ -1,0 +1,149 @@
+"""GPU parity of one Markov-clustering iteration (FP32) against the FP64
+oracle, stepwise: the oracle's input is the GPU's own previous output.
+Pattern decisions whose oracle value lies within relative 1e-4 of the prune
+threshold or of the top-k cut may go either way; everything else matches
+exactly, and kept values agree to relative 1e-4."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_21444_amd import synth
+from helpers import csr_from_json, load_golden, row_ids
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    from paper_2603_21444_amd import binding
+    assert torch.cuda.is_available()
+    binding.lib()
+    return binding
+
+
+def _check_step(X, got, r, prune, topk, rows=None):
+    """Compare the GPU output rows with the oracle on the same input X."""
+    n = X.shape[0]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    Xf = X.with_data(X.data.astype(np.float64))
+    cnt, cols, vals = oracle.mcl_rows(Xf, rows, r, prune, topk)
+    # pre-prune normalised values for the band rule
+    _, allc, allv = oracle.mcl_rows(Xf, rows, r, 0.0, 10 ** 9)
+    nflip = 0
+    for t, i in enumerate(rows):
+        s, e = int(got.indptr[i]), int(got.indptr[i + 1])
+        gc, gv = got.indices[s:e], got.data[s:e].astype(np.float64)
+        assert np.all(np.diff(gc) > 0), f"row {i} not canonical"
+        oc, ov = cols[t], vals[t]
+        if np.array_equal(gc, oc):
+            assert np.allclose(gv, ov, rtol=1e-4, atol=0), f"row {i} values"
+            continue
+        # pattern differs: every differing column must sit in the band
+        pre = dict(zip(allc[t].tolist(), allv[t].tolist()))
+        ranked = np.sort(allv[t])[::-1]
+        kth = ranked[min(topk, ranked.size) - 1] if ranked.size else 0.0
+        for j in set(gc.tolist()) ^ set(oc.tolist()):
+            v = pre[j]
+            near_prune = abs(v - prune) <= 1e-4 * prune
+            near_kth = abs(v - kth) <= 1e-4 * kth
+            assert near_prune or near_kth, f"row {i} col {j}: value {v} outside the band"
+            nflip += 1
+    return nflip
+
+
+def test_hand_worked_golden(B):
+    g = load_golden("mcl_hand.json")
+    X = csr_from_json(g["X"], np.float32)
+    for case in g["cases"]:
+        Y = B.mcl_iteration(B.to_device(X), 2, case["prune"], case["topk"]).to_host()
+        for i, (ecols, evals) in enumerate(case["rows"]):
+            s, e = Y.indptr[i], Y.indptr[i + 1]
+            assert Y.indices[s:e].tolist() == ecols
+            assert np.allclose(Y.data[s:e], [p / q for p, q in evals], rtol=2e-6, atol=0)
+
+
+@pytest.mark.parametrize("b", [4, 64, 256])
+def test_block_fixed_point_ten_iterations(B, b):
+    nb = 5
+    n = b * nb
+    perm = synth.rng_for(b).permutation(n)
+    rows, cols = [], []
+    for blk in perm.reshape(nb, b):
+        for i in blk:
+            for j in blk:
+                rows.append(i); cols.append(j)
+    rows, cols = np.array(rows), np.array(cols)
+    order = np.lexsort((cols, rows))
+    ip = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=ip[1:])
+    X = synth.HostCSR((n, n), ip, cols[order].astype(np.int32), np.full(n * b, 1.0 / b, np.float32))
+    Y = B.to_device(X)
+    for _ in range(10):
+        Y = B.mcl_iteration(Y, 2, 1e-4, 1000)
+    H = Y.to_host()
+    assert np.array_equal(H.indptr, X.indptr)
+    assert np.array_equal(H.indices, X.indices)
+    assert np.array_equal(H.data, X.data)
+
+
+@pytest.mark.parametrize("topk", [1000, 8, 2])
+def test_ties_and_topk_on_blocks(B, topk):
+    """Equal entries: top-k keeps the smallest columns of each block."""
+    b, nb = 16, 8
+    n = b * nb
+    rows = np.repeat(np.arange(n), b)
+    cols = (rows // b) * b + np.tile(np.arange(b), n)
+    X = synth.HostCSR((n, n), np.arange(n + 1, dtype=np.int64) * b, cols.astype(np.int32),
+                      np.full(n * b, 1.0 / b, np.float32))
+    got = B.mcl_iteration(B.to_device(X), 2, 1e-4, topk).to_host()
+    assert _check_step(X, got, 2, 1e-4, topk) == 0
+
+
+@pytest.mark.parametrize("n,d", [(3000, 12), (20000, 24)])
+def test_stepwise_random(B, n, d):
+    X = synth.mcl_matrix(n, d, 31, np.float32)
+    Y = B.to_device(X)
+    Xh = X
+    for it in range(3):
+        Yn = B.mcl_iteration(Y, 2, 1e-4, 1000)
+        got = Yn.to_host()
+        rows = None if n <= 3000 else np.sort(synth.rng_for(it, 5).choice(n, 1500, replace=False))
+        _check_step(Xh, got, 2, 1e-4, 1000, rows)
+        sums = np.bincount(row_ids(got), weights=got.data.astype(np.float64), minlength=n)
+        assert np.allclose(sums, 1.0, atol=1e-5)
+        assert np.diff(got.indptr).max() <= 1000 and np.diff(got.indptr).min() >= 1
+        Y, Xh = Yn, got
+
+
+def test_heavy_rows_and_topk_threshold(B):
+    """Rows with tens of thousands of products go through the bitmap kernel;
+    small topk exercises the threshold search there."""
+    n = 30000
+    X = synth.mcl_matrix(n, 6, 41, np.float32)
+    # make 3 columns of M dense-ish: rows of X with 4000 entries
+    rng = synth.rng_for(41, 2)
+    ip, ind, dat = [0], [], []
+    for i in range(n):
+        c, v = X.row(i)
+        if i in (7, 1234, 29999):
+            c = np.sort(rng.choice(n, 4000, replace=False)).astype(np.int32)
+            v = (1.0 - rng.random(4000))
+            v = (v / v.sum()).astype(np.float32)
+        ind.append(c); dat.append(v); ip.append(ip[-1] + len(c))
+    X = synth.HostCSR((n, n), np.array(ip, dtype=np.int64), np.concatenate(ind).astype(np.int32),
+                      np.concatenate(dat).astype(np.float32))
+    for topk, prune in [(1000, 1e-4), (50, 0.0), (3, 1e-6)]:
+        got = B.mcl_iteration(B.to_device(X), 2, prune, topk).to_host()
+        rows = np.array([7, 1234, 29999] + list(range(0, n, 97)))
+        _check_step(X, got, 2, prune, topk, rows)
+
+
+def test_handover_path_forced(B):
+    """A one-slot probe window sends most rows to the bitmap kernel: same
+    results."""
+    X = synth.mcl_matrix(4000, 10, 43, np.float32)
+    t = B.default_tuning()
+    t.max_window = 1
+    got = B.mcl_iteration(B.to_device(X), 2, 1e-4, 1000, plan=B.Plan(tuning=t)).to_host()
+    _check_step(X, got, 2, 1e-4, 1000)
