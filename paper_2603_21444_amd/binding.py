@@ -227,14 +227,17 @@ class Plan:
         return int(nnz.value), int(prod.value)
 
     # ---- product C = sum_k A_k B_k
-    def symbolic(self, As, Bs, capacity: int | None = None, stream=None):
+    def symbolic(self, As, Bs, capacity: int | None = None, stream=None, rp=None):
+        """Symbolic pass; eager (returns nnz) unless `capacity` is given, in
+        which case nothing is read back and the call is graph-capturable."""
         torch = _torch()
         K = len(As)
         m, n = As[0].shape[0], Bs[0].shape[1]
         dev = As[0].row_ptr.device
         kmax = max(A.shape[1] for A in As)
         ws = self.workspace(m, n, kmax, dev)
-        rp = torch.empty(m + 1, dtype=torch.int32, device=dev)
+        if rp is None:
+            rp = torch.empty(m + 1, dtype=torch.int32, device=dev)
         nnz = C.c_int64(-1)
         eager = capacity is None
         _check(lib().spgemm_symbolic(self.h, K, _arr(As), _arr(Bs), _ptr(rp),
@@ -330,9 +333,12 @@ def mcl_workspace_size(n: int, topk: int) -> int:
 
 
 def mcl_iteration(X: DeviceCSR, r: int = 2, prune: float = 1e-4, topk: int = 1000,
-                  plan: Plan | None = None, out=None, stream=None) -> DeviceCSR:
+                  plan: Plan | None = None, out=None, stream=None,
+                  capture: bool = False) -> DeviceCSR:
     """One Markov-clustering iteration on X = M^T (FP32).  `out` may hold
-    preallocated (row_ptr, col_idx, vals) of capacity n*min(topk, n)."""
+    preallocated (row_ptr, col_idx, vals) of capacity n*min(topk, n).  With
+    capture=True nothing is read back (graph-capturable); the result then
+    spans the whole capacity and its length is row_ptr[n]."""
     torch = _torch()
     plan = plan or Plan()
     n = X.shape[0]
@@ -349,7 +355,10 @@ def mcl_iteration(X: DeviceCSR, r: int = 2, prune: float = 1e-4, topk: int = 100
     nnz = C.c_int64(-1)
     x = X.spg()
     _check(lib().spgemm_mcl_iteration(plan.h, C.byref(x), r, C.c_float(prune), topk, _ptr(rp),
-                                      _ptr(col), _ptr(vals), cap, C.byref(nnz), _ptr(plan.ws),
+                                      _ptr(col), _ptr(vals), cap,
+                                      None if capture else C.byref(nnz), _ptr(plan.ws),
                                       plan.ws.numel(), _stream(stream)), "spgemm_mcl_iteration")
+    if capture:
+        return DeviceCSR((n, n), rp, col, vals)
     k = int(nnz.value)
     return DeviceCSR((n, n), rp, col[:k], vals[:k])

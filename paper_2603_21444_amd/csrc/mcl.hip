@@ -77,8 +77,7 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
     if (l == 0) rowflag[rslot] = 0;
     group_sync<BLOCK>();
     // 1. expansion E = X X (accumulate row i)
-    for_each_product<BLOCK, true, G, kMclUnroll, float>(
-        pr, i, true, l, lS, st, [&](int col, float v) {
+    auto fins = each_product([&](int col, float v) {
           int h = (int)mono_slot((uint32_t)col, mul);
           int d = 0;
           int old = atomicCAS(&key[h], kEmpty, (int)((uint32_t)col | 0x80000000u));
@@ -93,6 +92,7 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
           }
           lds_add(&val[h], v);
         });
+    for_each_product<BLOCK, true, G, kMclUnroll, float>(pr, i, true, l, lS, st, fins);
     group_sync<BLOCK>();
     if (rowflag[rslot]) {  // redone by the heavy kernel
       if (l == 0) fb_rows[atomicAdd(&hdr->fallback_count, 1)] = i;
@@ -256,15 +256,15 @@ __global__ __launch_bounds__(1024) void k_mcl_heavy(
     const int i = ri < nheavy ? rows[start + ri] : fb_rows[ri - nheavy];
     for (int w = tid; w < nw; w += 1024) map[w] = 0u;
     __syncthreads();
-    for_each_product<true, false, 1024, kMclUnroll, float>(pr, i, true, tid, lS, st,
-                                                           [&](int col, float) {
+    auto fmark = each_product([&](int col, float) {
       const uint32_t bit = 1u << (col & 31);
       if (!(atomicOr(&map[col >> 5], bit) & bit)) acc[col] = 0.f;
     });
+    for_each_product<true, false, 1024, kMclUnroll, float>(pr, i, true, tid, lS, st, fmark);
     __threadfence();
     __syncthreads();
-    for_each_product<true, true, 1024, kMclUnroll, float>(pr, i, true, tid, lS, st,
-                                                          [&](int col, float v) { global_add(&acc[col], v); });
+    auto fadd = each_product([&](int col, float v) { global_add(&acc[col], v); });
+    for_each_product<true, true, 1024, kMclUnroll, float>(pr, i, true, tid, lS, st, fadd);
     __threadfence();
     __syncthreads();
     // inflation + sum

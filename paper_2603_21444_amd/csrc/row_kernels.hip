@@ -15,7 +15,19 @@
 
 namespace spg {
 
-constexpr int kUnroll = 4;  // entries per lane in flight
+// Products per lane handed to one batched insert, and the occupancy the
+// row kernels are compiled for (waves per SIMD; bounds the registers).
+#ifndef SPG_SYM_UNROLL
+#define SPG_SYM_UNROLL 4
+#endif
+#ifndef SPG_NUM_UNROLL
+#define SPG_NUM_UNROLL 2
+#endif
+#ifndef SPG_NUM_WAVES
+#define SPG_NUM_WAVES 8
+#endif
+constexpr int kUnroll = SPG_NUM_UNROLL;
+constexpr int kSymUnroll = SPG_SYM_UNROLL;
 
 // Geometry of a row group of G lanes: groups of at most 64 lanes share a
 // 256-thread block (R rows per block, each wave's groups independent);
@@ -36,6 +48,37 @@ __device__ __forceinline__ int uniform_if_wave(int v) {
 
 // ---------------------------------------------------------------------------
 // a3: exact distinct-column count of each row with an LDS hash set.
+//
+// Inserts take the products of a lane N at a time: the first probe of all N
+// is issued before any result is examined, so a wave keeps N LDS atomics in
+// flight instead of waiting on each one (the inserts are latency-bound, not
+// throughput-bound).
+struct SymInsert {
+  int *tab;
+  int T, log2T;
+  int fresh;
+  template <int N, typename VT>
+  __device__ __forceinline__ void batch(const int (&col)[N], const VT (&)[N]) {
+    uint32_t h[N];
+    int old[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      h[u] = scramble_slot((uint32_t)col[u], log2T);
+      old[u] = col[u] >= 0 ? atomicCAS(&tab[h[u]], kEmpty, col[u]) : col[u];
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      if (col[u] < 0) continue;
+      int o = old[u];
+      uint32_t hh = h[u];
+      while (o != kEmpty && o != col[u]) {
+        hh = (hh + 1) & (T - 1);
+        o = atomicCAS(&tab[hh], kEmpty, col[u]);
+      }
+      fresh += (o == kEmpty) ? 1 : 0;
+    }
+  }
+};
 template <int G>
 __global__ __launch_bounds__(Geom<G>::WG) void k_sym_rows(const Problem *__restrict__ pr,
                                                           const int32_t *__restrict__ rows,
@@ -60,18 +103,9 @@ __global__ __launch_bounds__(Geom<G>::WG) void k_sym_rows(const Problem *__restr
     for (int s = l; s < T / 4; s += G) t4[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
     if (l == 0) *rowcnt = 0;
     group_sync<GM::BLOCK>();
-    int mine = 0;
-    for_each_product<GM::BLOCK, false, G, kUnroll, float>(
-        pr, i, true, l, lS, st, [&](int col, float) {
-          uint32_t h = scramble_slot((uint32_t)col, log2T);
-          while (true) {
-            const int old = atomicCAS(&tab[h], kEmpty, col);
-            if (old == kEmpty) { ++mine; break; }
-            if (old == col) break;
-            h = (h + 1) & (T - 1);
-          }
-        });
-    if (mine) atomicAdd(rowcnt, mine);
+    SymInsert ins{tab, T, log2T, 0};
+    for_each_product<GM::BLOCK, false, G, kSymUnroll, float>(pr, i, true, l, lS, st, ins);
+    if (ins.fresh) atomicAdd(rowcnt, ins.fresh);
     group_sync<GM::BLOCK>();
     if (l == 0) cnt[i] = *rowcnt;
   }
@@ -103,8 +137,75 @@ struct KeyCode {
   __device__ static int adj(int w) { return PACK ? (int)((uint32_t)w >> 24) - 128 : 0; }
 };
 
+template <typename VT, bool PACK, bool PLAIN>
+struct NumInsert {
+  using KC = KeyCode<PACK>;
+  int *key;
+  VT *val;
+  int *adj;
+  int *flag;
+  uint32_t mul;
+  int maxwin;
+  template <int N>
+  __device__ __forceinline__ void batch(const int (&col)[N], const VT (&v)[N]) {
+    int h[N], old[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      h[u] = (int)mono_slot((uint32_t)col[u], mul);
+      old[u] = col[u] >= 0 ? atomicCAS(&key[h[u]], kEmpty, KC::make(col[u])) : kEmpty;
+    }
+    int d[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      d[u] = 0;
+      if (col[u] < 0) continue;
+      while (old[u] != kEmpty && KC::col(old[u]) != col[u]) {
+        if (d[u] == maxwin) {  // long probe: the fallback redoes this row
+          *flag = 1;
+          d[u] = -1;
+          break;
+        }
+        ++d[u];
+        ++h[u];  // h <= home + maxwin < TT
+        old[u] = atomicCAS(&key[h[u]], kEmpty, KC::make(col[u]));
+      }
+    }
+    if (PLAIN) {
+      // wave group: the first insert of a column stores its value, repeats
+      // add after the fence (all of this batch's stores precede them)
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (col[u] >= 0 && d[u] >= 0 && old[u] == kEmpty) val[h[u]] = v[u];
+      group_sync<false>();
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (col[u] >= 0 && d[u] >= 0 && old[u] != kEmpty) lds_add(&val[h[u]], v[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (col[u] >= 0 && d[u] >= 0) lds_add(&val[h[u]], v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      if (col[u] < 0 || d[u] <= 0 || old[u] != kEmpty) continue;
+      int larger = 0;
+      for (int t = h[u] - d[u]; t < h[u]; ++t) {
+        if (KC::col(key[t]) > col[u]) {
+          if (PACK) atomicAdd(&key[t], 1 << 24);
+          else atomicAdd(&adj[t], 1);
+          ++larger;
+        }
+      }
+      if (larger) {
+        if (PACK) atomicSub(&key[h[u]], larger << 24);
+        else atomicSub(&adj[h[u]], larger);
+      }
+    }
+  }
+};
+
 template <int G, typename VT, bool PACK>
-__global__ __launch_bounds__(Geom<G>::WG) void k_num_rows(const Problem *__restrict__ pr,
+__global__ __launch_bounds__(Geom<G>::WG, SPG_NUM_WAVES) void k_num_rows(const Problem *__restrict__ pr,
                                                           const int32_t *__restrict__ rows,
                                                           WsHeader *__restrict__ hdr, int bin,
                                                           int lS, int TT, uint32_t mul,
@@ -132,7 +233,7 @@ __global__ __launch_bounds__(Geom<G>::WG) void k_num_rows(const Problem *__restr
   if (hdr->status) return;
   const int count = hdr->bin_count[bin];
   const int start = hdr->bin_start[bin];
-  const int c = TT / G;  // slots per lane in the output pass (odd)
+  const int c = TT / G;  // slots per lane in the output pass of block groups (odd)
   for (int ri = blockIdx.x * GM::R + rslot; ri < count; ri += gridDim.x * GM::R) {
     const int i = uniform_if_wave<G>(rows[start + ri]);
     {
@@ -142,60 +243,54 @@ __global__ __launch_bounds__(Geom<G>::WG) void k_num_rows(const Problem *__restr
         int4 *a4 = reinterpret_cast<int4 *>(adj);
         for (int s = l; s < TT / 4; s += G) a4[s] = make_int4(0, 0, 0, 0);
       }
-      for (int s = l; s < TT; s += G) val[s] = VT(0);
+      if (GM::BLOCK)
+        for (int s = l; s < TT; s += G) val[s] = VT(0);
     }
     if (l == 0) rowflag[rslot] = 0;
     group_sync<GM::BLOCK>();
-    for_each_product<GM::BLOCK, true, G, kUnroll, VT>(
-        pr, i, true, l, lS, st, [&](int col, VT v) {
-          int h = (int)mono_slot((uint32_t)col, mul);
-          int d = 0;
-          int old = atomicCAS(&key[h], kEmpty, KC::make(col));
-          while (old != kEmpty && KC::col(old) != col) {
-            if (d == maxwin) {  // long probe: the fallback redoes this row
-              rowflag[rslot] = 1;
-              return;
-            }
-            ++d;
-            ++h;  // h <= home + maxwin < TT
-            old = atomicCAS(&key[h], kEmpty, KC::make(col));
-          }
-          lds_add(&val[h], v);
-          if (old == kEmpty && d > 0) {
-            int larger = 0;
-            for (int t = h - d; t < h; ++t) {
-              if (KC::col(key[t]) > col) {
-                if (PACK) atomicAdd(&key[t], 1 << 24);
-                else atomicAdd(&adj[t], 1);
-                ++larger;
-              }
-            }
-            if (larger) {
-              if (PACK) atomicSub(&key[h], larger << 24);
-              else atomicSub(&adj[h], larger);
-            }
-          }
-        });
+    NumInsert<VT, PACK, !GM::BLOCK> ins{key, val, adj, rowflag + rslot, mul, maxwin};
+    for_each_product<GM::BLOCK, true, G, kUnroll, VT>(pr, i, true, l, lS, st, ins);
     group_sync<GM::BLOCK>();
     const bool ok = rowflag[rslot] == 0;
     const int rs = crp[i];
     const int nnz = crp[i + 1] - rs;
-    const int s0 = l * c;
-    int mine = 0;
-    for (int j = 0; j < c; ++j) mine += key[s0 + j] != kEmpty;
     int total;
-    int r = group_excl_scan<GM::BLOCK, G>(mine, l, wtot, total);
-    if (ok && nnz > 0) {
-      SPG_GLOBAL int32_t *cb = gpw(ccol) + rs;
-      SPG_GLOBAL VT *vb = gpw(cval) + rs;
-      for (int j = 0; j < c; ++j) {
-        const int w = key[s0 + j];
-        if (w != kEmpty) {
-          int rr = r + (PACK ? KC::adj(w) : adj[s0 + j]);
+    SPG_GLOBAL int32_t *cb = gpw(ccol) + rs;
+    SPG_GLOBAL VT *vb = gpw(cval) + rs;
+    if (!GM::BLOCK) {
+      // slots s0 + l of each round: one ballot gives every lane its rank
+      const int g0 = (lane_id() / G) * G;
+      const uint64_t gm = (G >= kWave) ? ~0ull : (((1ull << G) - 1ull) << g0);
+      const uint64_t below = lanes_below();
+      int base = 0;
+      for (int s0 = 0; s0 < TT; s0 += G) {
+        const int s = s0 + l;
+        const int w = key[s];
+        const uint64_t m = __ballot(w != kEmpty) & gm;
+        if (ok && w != kEmpty && nnz > 0) {
+          int rr = base + __popcll(m & below) + (PACK ? KC::adj(w) : adj[s]);
           rr = rr < 0 ? 0 : (rr >= nnz ? nnz - 1 : rr);  // in bounds even for a changed pattern
           cb[(uint32_t)rr] = KC::col(w);
-          vb[(uint32_t)rr] = val[s0 + j];
-          ++r;
+          vb[(uint32_t)rr] = val[s];
+        }
+        base += __popcll(m);
+      }
+      total = base;
+    } else {
+      const int s0 = l * c;
+      int mine = 0;
+      for (int j = 0; j < c; ++j) mine += key[s0 + j] != kEmpty;
+      int r = group_excl_scan<GM::BLOCK, G>(mine, l, wtot, total);
+      if (ok && nnz > 0) {
+        for (int j = 0; j < c; ++j) {
+          const int w = key[s0 + j];
+          if (w != kEmpty) {
+            int rr = r + (PACK ? KC::adj(w) : adj[s0 + j]);
+            rr = rr < 0 ? 0 : (rr >= nnz ? nnz - 1 : rr);
+            cb[(uint32_t)rr] = KC::col(w);
+            vb[(uint32_t)rr] = val[s0 + j];
+            ++r;
+          }
         }
       }
     }
@@ -243,7 +338,7 @@ __global__ __launch_bounds__(1024) void k_num_fallback(const Problem *__restrict
       val[s] = VT(0);
     }
     __syncthreads();
-    for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, [&](int col, VT v) {
+    auto fins = each_product([&](int col, VT v) {
       uint32_t h = scramble_slot((uint32_t)col, log2T);
       for (int probes = 0;; ++probes) {
         const int old = atomicCAS(&key[h], kEmpty, col);
@@ -258,6 +353,7 @@ __global__ __launch_bounds__(1024) void k_num_fallback(const Problem *__restrict
         h = (h + 1) & (T - 1);
       }
     });
+    for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fins);
     __syncthreads();
     // in-place compaction in slot order (a round's reads precede its writes)
     int pre = 0;
@@ -331,12 +427,12 @@ __global__ __launch_bounds__(1024) void k_sym_heavy(const Problem *__restrict__ 
     if (!LDSMAP) __threadfence();
     __syncthreads();
     int mine = 0;
-    for_each_product<true, false, 1024, kUnroll, float>(pr, i, true, tid, lS, st,
-                                                        [&](int col, float) {
+    auto fmark = each_product([&](int col, float) {
       const uint32_t bit = 1u << (col & 31);
       const uint32_t old = atomicOr(&map[col >> 5], bit);
       mine += (old & bit) ? 0 : 1;
     });
+    for_each_product<true, false, 1024, kUnroll, float>(pr, i, true, tid, lS, st, fmark);
     if (mine) atomicAdd(&total, mine);
     __syncthreads();
     if (tid == 0) cnt[i] = total;
@@ -374,18 +470,18 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
     for (int w = tid; w < nw; w += 1024) map[w] = 0u;
     __threadfence();
     __syncthreads();
-    for_each_product<true, false, 1024, kUnroll, VT>(pr, i, true, tid, lS, st,
-                                                     [&](int col, VT) {
+    auto fmark = each_product([&](int col, VT) {
       const uint32_t bit = 1u << (col & 31);
       const uint32_t old = atomicOr(&map[col >> 5], bit);
       if (!(old & bit)) acc[col] = VT(0);
     });
+    for_each_product<true, false, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fmark);
     // the accumulator lives in global memory: complete this pass's stores
     // at device scope and drop stale L1 lines before the next pass
     __threadfence();
     __syncthreads();
-    for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st,
-                                                    [&](int col, VT v) { global_add(&acc[col], v); });
+    auto fadd = each_product([&](int col, VT v) { global_add(&acc[col], v); });
+    for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fadd);
     __threadfence();
     __syncthreads();
     const int rs = crp[i];
@@ -463,11 +559,11 @@ size_t sym_lds_bytes(int b, int G) {
   return (size_t)R * bin_slots(b) * 4 + (size_t)2 * R * G * 4 + (size_t)R * 4 + 64;
 }
 
-// Table slots of a numeric row: T + at least kTail, as G lanes times an odd
-// chunk length (the output pass reads chunks without LDS bank conflicts).
+// Table slots of a numeric row: T + at least kTail, a multiple of G (block
+// groups: G times an odd chunk length, read without LDS bank conflicts).
 int num_table_slots(int b, int G) {
   int c = (bin_slots(b) + kTail + G - 1) / G;
-  if (!(c & 1)) ++c;
+  if (G > kWave && !(c & 1)) ++c;  // block groups read chunks of c slots
   return c * G;
 }
 

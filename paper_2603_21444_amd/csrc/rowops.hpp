@@ -113,7 +113,9 @@ struct Stage {
   VT *a;     // value a_ik
 };
 
-// Calls f(col, a_ik * b_kj) for every product of row i.  The entries of an
+// Hands every product (col, a_ik * b_kj) of row i to f.batch<N>(cols, vals)
+// (N products per lane at once, col < 0 = no product), so that f can issue
+// the LDS operations of N products before waiting on any of them.  The entries of an
 // A row are taken in chunks of G: lane l stages entry c0+l in LDS (one
 // coalesced read of A, one gather of B row bounds).  Then S = 2^lS lanes
 // share each entry: lane l reads position (l mod S) of the B rows of
@@ -123,7 +125,7 @@ struct Stage {
 template <bool BLOCK, bool VALUES, int G, int U, typename VT, typename F>
 __device__ __forceinline__ void for_each_product(const Problem *__restrict__ pr, int i,
                                                  bool active, int l, int lS, Stage<VT> st,
-                                                 F &&f) {
+                                                 F &f) {
   const int K = pr->K;
   const int S = 1 << lS;
   const int ES = G >> lS;
@@ -169,9 +171,7 @@ __device__ __forceinline__ void for_each_product(const Problem *__restrict__ pr,
             if (VALUES) v[u] = st.a[ee] * bval[idx];
           }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (col[u] >= 0) f(col[u], v[u]);
+        f.template batch<U>(col, v);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int ee = t0 + ES * u;
@@ -179,7 +179,9 @@ __device__ __forceinline__ void for_each_product(const Problem *__restrict__ pr,
             const int len = st.len[ee];
             for (int q = q0 + S; q < len; q += S) {
               const int idx = st.b0[ee] + q;
-              f(bcol[idx], VALUES ? st.a[ee] * bval[idx] : VT(0));
+              int c1[1] = {bcol[idx]};
+              VT v1[1] = {VALUES ? st.a[ee] * bval[idx] : VT(0)};
+              f.template batch<1>(c1, v1);
             }
           }
         }
@@ -187,6 +189,22 @@ __device__ __forceinline__ void for_each_product(const Problem *__restrict__ pr,
       group_sync<BLOCK>();
     }
   }
+}
+
+// Adapter for per-product callbacks: f(col, val) for each valid product.
+template <typename F>
+struct EachProduct {
+  F f;
+  template <int N, typename VT>
+  __device__ __forceinline__ void batch(const int (&col)[N], const VT (&v)[N]) {
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      if (col[u] >= 0) f(col[u], v[u]);
+  }
+};
+template <typename F>
+__device__ __forceinline__ EachProduct<F> each_product(F f) {
+  return EachProduct<F>{f};
 }
 
 }  // namespace spg

@@ -1,0 +1,116 @@
+"""Captured stage graphs: every replay matches the eager result (several
+replays, with eager work and synchronisation between them)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_21444_amd import synth
+from helpers import assert_same_csr, row_ids
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    from paper_2603_21444_amd import binding
+    assert torch.cuda.is_available()
+    binding.lib()
+    return binding
+
+
+def _pairs(dtype, kind, seed=3, K=5):
+    m, kk, n = 4000, 30000, 12000
+    A = synth.varnnz_csr(m, kk, 4, 32, seed, dtype, kind, stream=0)
+    Bm = synth.varnnz_csr(kk, n, 4, 32, seed, dtype, kind, stream=1)
+    bounds = synth.column_blocks(kk, K, kk // 10, kk // 3, seed)
+    return synth.split_inner(A, Bm, bounds)
+
+
+def test_stage_graph_replays_match_eager_exactly(B):
+    import torch
+    from paper_2603_21444_amd.graph import StageGraph
+    pairs = _pairs(np.float64, "int")
+    dp = [(B.to_device(a), B.to_device(b)) for a, b in pairs]
+    eager = B.batched(dp).to_host()
+    g = StageGraph(dp)
+    for rep in range(4):
+        g.replay()
+        got = g.result().to_host()
+        assert np.array_equal(got.indptr, eager.indptr), rep
+        assert np.array_equal(got.indices, eager.indices), rep
+        assert np.array_equal(got.data, eager.data), rep  # integer values: exact
+        # eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        float((x * x).sum())
+        B.spgemm(*dp[0])
+        torch.cuda.synchronize()
+
+
+def test_stage_graph_fp32_against_oracle(B):
+    from paper_2603_21444_amd.graph import StageGraph
+    pairs = _pairs(np.float32, "normal", seed=5, K=8)
+    dp = [(B.to_device(a), B.to_device(b)) for a, b in pairs]
+    g = StageGraph(dp)
+    ref, S = oracle.batched([(a.astype(np.float64), b.astype(np.float64)) for a, b in pairs],
+                            with_abs=True)
+    for _ in range(3):
+        g.replay()
+        assert_same_csr(g.result().to_host(), ref, S, np.float32, what="graph")
+
+
+def test_stage_graph_capacity_error_surfaces(B):
+    from paper_2603_21444_amd.graph import StageGraph
+    pairs = _pairs(np.float32, "normal", seed=7, K=3)
+    dp = [(B.to_device(a), B.to_device(b)) for a, b in pairs]
+    g = StageGraph(dp, capacity=1000)
+    g.replay()
+    with pytest.raises(B.SpgError) as e:
+        g.result()
+    assert e.value.code == B.SPG_ERR_CAPACITY
+
+
+def test_mcl_graph_fixed_point_and_replays(B):
+    import torch
+    from paper_2603_21444_amd.graph import MCLGraph
+    b, nb = 32, 12
+    n = b * nb
+    perm = synth.rng_for(9).permutation(n)
+    rows, cols = [], []
+    for blk in perm.reshape(nb, b):
+        for i in blk:
+            for j in blk:
+                rows.append(i); cols.append(j)
+    rows, cols = np.array(rows), np.array(cols)
+    order = np.lexsort((cols, rows))
+    ip = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=ip[1:])
+    X = synth.HostCSR((n, n), ip, cols[order].astype(np.int32), np.full(n * b, 1.0 / b, np.float32))
+    g = MCLGraph(B.to_device(X), iters=10)
+    for _ in range(3):
+        g.replay()
+        H = g.result().to_host()
+        assert np.array_equal(H.indptr, X.indptr)
+        assert np.array_equal(H.indices, X.indices)
+        assert np.array_equal(H.data, X.data)
+        torch.cuda.synchronize()
+
+
+def test_mcl_graph_matches_eager_iterations(B):
+    X = synth.mcl_matrix(5000, 16, 13, np.float32)
+    from paper_2603_21444_amd.graph import MCLGraph
+    dX = B.to_device(X)
+    Y = dX
+    for _ in range(4):
+        Y = B.mcl_iteration(Y)
+    eager = Y.to_host()
+    g = MCLGraph(dX, iters=4)
+    for _ in range(2):
+        g.replay()
+        got = g.result().to_host()
+        # FP32 atomics may order sums differently between runs: compare the
+        # invariants and the bulk of the pattern
+        sums = np.bincount(row_ids(got), weights=got.data.astype(np.float64), minlength=5000)
+        assert np.allclose(sums, 1.0, atol=1e-5)
+        same = np.mean(np.diff(got.indptr) == np.diff(eager.indptr))
+        assert same > 0.99
