@@ -12,9 +12,10 @@ inputs resident in HBM.  Prints one JSON line.
              stream it runs on, against 8 TB/s
   cpu_baseline  the FP64 oracle on the host cores, same inputs
 
-Extra workloads (--extra): the batched stage sequence (8 block products
-summed into one C, eager per-block launches + merge vs one fused pass in a
-captured graph) and the backward pass at fixed sparsity.
+Also reported (unless --only-plain): the batched stage sequence (8 uneven
+block products summed into one C; per-block eager launches + sparse sum vs
+the fused product captured as one graph) and the backward pass at fixed
+sparsity; with --mcl, 10 Markov-clustering iterations in one graph.
 """
 from __future__ import annotations
 
@@ -86,9 +87,8 @@ def cpu_baseline(A, B, budget_s):
     import oracle
     Af, Bf = A.astype(np.float64), B.astype(np.float64)
     oracle.spgemm(oracle_sample(Af, 1024), Bf)  # warm the library and caches
-    runs, t_total, products = 0, 0.0, 0
-    ub = oracle.rowub(Af, Bf)
-    total_products = int(ub.sum())
+    runs, t_total = 0, 0.0
+    total_products = int(oracle.rowub(Af, Bf).sum())
     while runs < 1 or (t_total < budget_s and runs < 6):
         t0 = time.perf_counter()
         C = oracle.spgemm(Af, Bf)
@@ -108,6 +108,154 @@ def oracle_sample(M, rows):
     return HostCSR((rows, M.shape[1]), M.indptr[:rows + 1], M.indices[:e], M.data[:e])
 
 
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def bench_batched(args):
+    """8 uneven block products summed into one C: per-block eager launches
+    (symbolic with read-back + numeric per block, then the sparse sum) vs the
+    fused product captured as one graph."""
+    import torch
+    from paper_2603_21444_amd import binding, synth
+    from paper_2603_21444_amd.graph import StageGraph
+    m, n, K = 1 << 18, 1 << 20, 8
+    rng = synth.rng_for(SEED + 3, 11)
+    kdims = rng.integers(1 << 18, (1 << 20) + 1, size=K)
+    pairs = []
+    for k in range(K):
+        Ak = synth.varnnz_csr(m, int(kdims[k]), 4, 32, SEED + 3, np.float32, "normal", stream=2 * k)
+        Bk = synth.varnnz_csr(int(kdims[k]), n, 4, 32, SEED + 3, np.float32, "normal", stream=2 * k + 1)
+        pairs.append((binding.to_device(Ak), binding.to_device(Bk)))
+        log(f"[bench] batched block {k}: K_k={int(kdims[k])}")
+    bytes_in = sum(csr_bytes(a.shape[0], a.nnz, 4) + csr_bytes(b.shape[0], b.nnz, 4) for a, b in pairs)
+
+    def eager():
+        parts = [binding.spgemm(a, b) for a, b in pairs]
+        return binding.merge(parts)
+
+    for _ in range(max(1, args.warmup)):
+        Ce = eager()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Ce = eager()
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    nnz = Ce.nnz
+    del Ce
+    torch.cuda.empty_cache()
+    g = StageGraph(pairs)
+    for _ in range(max(1, args.warmup)):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    Cg = g.result()
+    assert Cg.nnz == nnz, (Cg.nnz, nnz)
+    _, products = g.plan.info()
+    if products < 0:
+        plan = binding.Plan()
+        plan.symbolic([a for a, _ in pairs], [b for _, b in pairs])
+        _, products = plan.info()
+    alg = bytes_in + 4 * (m + 1) + 8 * nnz
+    return {
+        "workload": "C = sum_k A_k B_k, 8 blocks, m = 2^18, n = 2^20, inner K_k ~ U[2^18, 2^20], "
+                    "4..32 nnz/row, FP32 N(0,1)",
+        "products": int(products), "nnz_C": int(nnz),
+        "graph_ms": round(graph_ms, 3), "eager_per_block_ms": round(eager_ms, 3),
+        "graph_gflops": round(2 * products / graph_ms / 1e6, 2),
+        "eager_gflops": round(2 * products / eager_ms / 1e6, 2),
+        "graph_speedup": round(eager_ms / graph_ms, 3),
+        "graph_alg_GBs": round(alg / graph_ms / 1e6, 1),
+    }
+
+
+def bench_backward(args):
+    """Backward at fixed sparsity: A, B 2^18 x 2^18, 16 nnz/row, FP32 N(0,1),
+    loss <W, C> with W N(0,1) on S(C)."""
+    import torch
+    from paper_2603_21444_amd import binding, synth
+    n, d = 1 << 18, 16
+    A = synth.uniform_csr(n, n, d, SEED + 5, np.float32, "normal", stream=0)
+    B = synth.uniform_csr(n, n, d, SEED + 5, np.float32, "normal", stream=1)
+    dA_, dB_ = binding.to_device(A), binding.to_device(B)
+    plan = binding.Plan()
+    rp, nnz = plan.symbolic([dA_], [dB_])
+    col, vals = plan.numeric([dA_], [dB_], rp, nnz)
+    W = torch.from_numpy(synth.draw_values(synth.rng_for(SEED + 5, 9), nnz, "normal", np.float32)).cuda()
+    dC = binding.DeviceCSR((n, n), rp, col, W)
+    for _ in range(max(1, args.warmup)):
+        plan.backward(dA_, dB_, dC)
+    torch.cuda.synchronize()
+    ev = _events(2)
+    s = torch.cuda.current_stream()
+    ev[0].record(s)
+    for _ in range(args.steps):
+        plan.backward(dA_, dB_, dC)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    _, products = plan.info()
+    alg = csr_bytes(n, A.nnz, 4) + csr_bytes(n, B.nnz, 4) + 4 * (n + 1) + 8 * nnz + 4 * (A.nnz + B.nnz)
+    return {
+        "workload": "dA = (W B^T) on S(A), dB = (A^T W) on S(B); A, B 2^18 x 2^18, 16 nnz/row, FP32",
+        "products": int(products), "ms": round(ms, 4),
+        "gflops": round(4 * products / ms / 1e6, 2),
+        "alg_GBs": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+    }
+
+
+def bench_mcl(args):
+    """10 Markov-clustering iterations on n = 2^19 (24 + 1 per column), FP32,
+    recorded as one graph."""
+    import torch
+    from paper_2603_21444_amd import binding, synth
+    from paper_2603_21444_amd.graph import MCLGraph
+    n = 1 << 19
+    X = synth.mcl_matrix(n, 24, SEED + 4, np.float32)
+    g = MCLGraph(binding.to_device(X), iters=10)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    Y = g.result()
+    return {"workload": "MCL, n = 2^19, 24 + 1 nnz per column, r = 2, prune < 1e-4, top-1000, "
+                        "10 iterations in one graph",
+            "ms_10_iterations": round(ms, 2), "final_nnz": Y.nnz}
+
+
+def traffic_from_profile(kernel_src_hash):
+    """HBM bytes per launch of the numeric kernel from the committed counter
+    summary, if it was taken from the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "numeric_uniform2p20_fp32_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != kernel_src_hash:
+        return None
+    return d.get("traffic_bytes")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_21444_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +267,8 @@ def main():
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--only-plain", action="store_true", help="skip the batched and backward workloads")
+    ap.add_argument("--mcl", action="store_true", help="also time 10 MCL iterations (n = 2^19)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -155,17 +305,27 @@ def main():
             "rows": n, "nnz_per_row": d, "products": products, "nnz_C": r["nnz"], "seed": SEED + 1,
         },
         "roofline": {
-            "kernel": "numeric pass (k_num_hash)",
+            "kernel": "numeric pass (row-binned LDS-hash kernels, all bins of one step)",
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic_from_profile(kernel_source_hash()),
             "algorithmic_bytes": num_bytes,
             "numeric_ms": round(r["num_ms"], 4),
         },
     }
+    if not args.only_plain:
+        log("[bench] batched stage sequence")
+        out["batched_graph"] = bench_batched(args)
+        torch.cuda.empty_cache()
+        log("[bench] backward")
+        out["backward"] = bench_backward(args)
+        torch.cuda.empty_cache()
+    if args.mcl:
+        log("[bench] MCL")
+        out["mcl"] = bench_mcl(args)
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -1,0 +1,112 @@
+"""Autotuner for the row kernels' launch parameters.
+
+For each bin that carries a noticeable share of the work it times the
+symbolic + numeric passes (HIP events, eager, outside any graph capture)
+over a few candidate (lanes per row, lanes per A entry) pairs and keeps the
+fastest; the other bins keep their current setting.  Results are cached in
+a JSON file keyed by dtype, shape, number of block products and the
+rounded per-bin row histogram, so a capture reuses them without timing.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import binding
+
+BIN_EDGES = [0] + [8 << b for b in range(1, 12)]
+# candidate (lanes, sub) per bin size class
+CANDIDATES = {
+    1: [(8, 4), (8, 8), (16, 8)],
+    2: [(8, 8), (16, 8), (16, 16)],
+    3: [(16, 8), (16, 16), (32, 16)],
+    4: [(32, 8), (32, 16), (64, 16)],
+    5: [(64, 16), (64, 8), (32, 16), (64, 32)],
+    6: [(64, 16), (64, 32), (128, 16)],
+    7: [(64, 16), (128, 16), (256, 16)],
+    8: [(128, 16), (256, 16), (256, 32)],
+    9: [(256, 16), (512, 16)],
+    10: [(512, 16), (1024, 16)],
+    11: [(1024, 16)],
+}
+
+
+def default_cache_path() -> str:
+    base = os.environ.get("SPG_TUNING_CACHE", os.path.expanduser("~/.cache/paper_2603_21444_amd"))
+    return os.path.join(base, "tuning.json")
+
+
+def _key(As, Bs, dtype, counts) -> str:
+    hist = [0 if c == 0 else int(round(math.log2(c))) for c in counts]
+    return json.dumps([str(dtype), As[0].shape[0], Bs[0].shape[1], len(As), hist])
+
+
+def _time(As, Bs, tuning, reps: int) -> float:
+    plan = binding.Plan(tuning=tuning)
+    rp, nnz = plan.symbolic(As, Bs)
+    plan.numeric(As, Bs, rp, nnz)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        rp, nnz = plan.symbolic(As, Bs)
+        plan.numeric(As, Bs, rp, nnz)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(As, Bs, reps: int = 3, cache_path: str | None = None, share: float = 0.05,
+         use_cache: bool = True) -> binding.SpgTuning:
+    """Tuning for the product sum_k A_k B_k (DeviceCSR lists)."""
+    plan = binding.Plan()
+    plan.symbolic(As, Bs)
+    sym, num = plan.bins()
+    counts = [max(a, b) for a, b in zip(sym, num)]
+    dtype = As[0].vals.dtype if As[0].vals is not None else torch.float32
+    key = _key(As, Bs, dtype, counts)
+    path = cache_path or default_cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return _from_json(cache[key])
+    t = binding.default_tuning()
+    work = [counts[b] * BIN_EDGES[b] if 1 <= b <= 11 else 0 for b in range(len(counts))]
+    total = sum(work) or 1
+    for b in sorted(range(1, 12), key=lambda b: -work[b]):
+        if work[b] < share * total:
+            continue
+        best, best_ms = None, float("inf")
+        for lanes, sub in CANDIDATES[b]:
+            t.lanes[b], t.sub[b] = lanes, sub
+            ms = _time(As, Bs, t, reps)
+            if ms < best_ms:
+                best, best_ms = (lanes, sub), ms
+        t.lanes[b], t.sub[b] = best
+    if use_cache:
+        cache[key] = _to_json(t)
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return t
+
+
+def _to_json(t: binding.SpgTuning) -> dict:
+    return {"lanes": list(t.lanes), "sub": list(t.sub), "heavy_slots": t.heavy_slots,
+            "max_window": t.max_window}
+
+
+def _from_json(d: dict) -> binding.SpgTuning:
+    t = binding.default_tuning()
+    for b, v in enumerate(d["lanes"]):
+        t.lanes[b] = v
+    for b, v in enumerate(d["sub"]):
+        t.sub[b] = v
+    t.heavy_slots = d["heavy_slots"]
+    t.max_window = d["max_window"]
+    return t

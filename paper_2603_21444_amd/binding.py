@@ -34,7 +34,7 @@ EXPORTS = [
     "spgemm_plan_status", "spgemm_plan_info", "spgemm_status_string",
     "spgemm_symbolic", "spgemm_numeric", "spgemm_merge", "spgemm_backward",
     "spgemm_mcl_workspace_size", "spgemm_mcl_iteration",
-    "spgemm_default_tuning", "spgemm_plan_set_tuning",
+    "spgemm_default_tuning", "spgemm_plan_set_tuning", "spgemm_plan_bins",
 ]
 
 
@@ -84,6 +84,7 @@ def lib():
                                                C.POINTER(I64), P, C.c_size_t, P]),
             "spgemm_default_tuning": (C.c_int, [C.POINTER(SpgTuning)]),
             "spgemm_plan_set_tuning": (C.c_int, [P, C.POINTER(SpgTuning)]),
+            "spgemm_plan_bins": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -220,6 +221,13 @@ class Plan:
         s = C.c_int32(0)
         _check(lib().spgemm_plan_status(self.h, C.byref(s)), "spgemm_plan_status")
         return int(s.value)
+
+    def bins(self):
+        """(symbolic bin counts, numeric bin counts) after an eager symbolic call."""
+        s = (C.c_int32 * SPG_NBINS)()
+        n = (C.c_int32 * SPG_NBINS)()
+        _check(lib().spgemm_plan_bins(self.h, s, n), "spgemm_plan_bins")
+        return list(s), list(n)
 
     def info(self):
         nnz, prod = C.c_int64(0), C.c_int64(0)

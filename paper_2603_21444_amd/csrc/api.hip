@@ -26,6 +26,7 @@ struct spg_plan_s {
   int kdim[SPG_MAX_PARTS] = {0};
   int64_t annz[SPG_MAX_PARTS] = {0}, bnnz[SPG_MAX_PARTS] = {0};
   int num_count[kNB] = {0};
+  int sym_count[kNB] = {0};
   int64_t nnz = -1, products = -1;
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -79,6 +80,7 @@ const DevInfo &dev_info() {
   (void)configure_lds_limits(d.lds_per_block);
   (void)configure_backward_lds(d.lds_per_block);
   (void)configure_mcl_lds(d.lds_per_block);
+  (void)configure_wave_lds(d.lds_per_block);
   (void)hipGetLastError();
   g_dev.push_back(d);
   return g_dev.back();
@@ -239,6 +241,7 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
     rc = status_from_bits(p->host_hdr->status);
     if (rc) return rc;
     sbp = make_binplan(p, D.sym_maxbin, true, p->host_hdr->bin_count);
+    for (int b = 0; b < kNB; ++b) p->sym_count[b] = p->host_hdr->bin_count[b];
   } else {
     sbp = make_binplan(p, D.sym_maxbin, false, nullptr);
   }
@@ -402,6 +405,15 @@ const char *spgemm_status_string(int status) {
     case SPG_ERR_ARG: return "bad argument";
     default: return "unknown status";
   }
+}
+
+int spgemm_plan_bins(spg_plan plan, int32_t *sym_counts, int32_t *num_counts) {
+  if (!plan || !plan->counts_known) return SPG_ERR_ARG;
+  for (int b = 0; b < kNB; ++b) {
+    if (sym_counts) sym_counts[b] = plan->sym_count[b];
+    if (num_counts) num_counts[b] = plan->num_count[b];
+  }
+  return SPG_OK;
 }
 
 int spgemm_default_tuning(spg_tuning *t) {

@@ -25,9 +25,11 @@ __global__ void k_fill_zero(VT *p, int64_t n) {
     p[t] = VT(0);
 }
 
-// Products of row i, S lanes per A entry, with the entry's staged slot e
-// passed to f(col, b, e).  Chunks of G entries of the A row are staged in
-// LDS; `done(c0, nE)` runs after each chunk (group-synchronised).
+// Products of row i, S lanes per A entry: f(col, b, idx, e) handles product
+// (entry e, B position idx) and returns its contribution to dA_e, which the
+// entry's S lanes sum in registers and reduce with shuffles into sd[e].
+// Chunks of G entries of the A row are staged in LDS; `done(c0, nE)` runs
+// after each chunk (group-synchronised).
 template <bool BLOCK, int G, typename VT, typename F, typename D>
 __device__ __forceinline__ void for_each_product_e(const Part &P, int i, int l, int lS, int *sb,
                                                    int *sl, VT *sa, VT *sd, F &&f, D &&done) {
@@ -47,16 +49,19 @@ __device__ __forceinline__ void for_each_product_e(const Part &P, int i, int l, 
       sb[l] = b0;
       sl[l] = brp[r + 1] - b0;
       sa[l] = gp(static_cast<const VT *>(P.aval))[as + e];
-      sd[l] = VT(0);
     }
     const int nE = min(G, nA - c0);
     group_sync<BLOCK>();
     for (int ee = sg; ee < nE; ee += ES) {
       const int len = sl[ee];
+      VT part = VT(0);
       for (int q = q0; q < len; q += S) {
         const int idx = sb[ee] + q;
-        f(bcol[idx], bval[idx], idx, ee);
+        part += f(bcol[idx], bval[idx], idx, ee);
       }
+      // the S lanes of entry ee hold its partial sums: reduce, one store
+      for (int off = S / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, S);
+      if (q0 == 0) sd[ee] = part;
     }
     group_sync<BLOCK>();
     done(as + c0, nE);
@@ -122,13 +127,13 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
           while ((k2 = key[h]) != col) {
             if (k2 == kEmpty || ++probes > T) {  // product outside the given pattern
               atomicOr(&hdr->status, kStatInvalid);
-              return;
+              return VT(0);
             }
             h = (h + 1) & (T - 1);
           }
           const VT wij = wv[h];
-          if (dA) lds_add(&sd[ee], wij * b);
           if (dB) global_add(&dB[idx], sa[ee] * wij);
+          return wij * b;
         },
         [&](int p0, int nE) {
           if (dA && l < nE) dA[p0 + l] = sd[l];
@@ -164,8 +169,8 @@ __global__ __launch_bounds__(1024) void k_bwd_heavy(const Problem *__restrict__ 
         P, i, tid, lS, sb, sl, sa, sd,
         [&](int col, VT b, int idx, int ee) {
           const VT wij = dense[col];
-          if (dA) lds_add(&sd[ee], wij * b);
           if (dB) global_add(&dB[idx], sa[ee] * wij);
+          return wij * b;
         },
         [&](int p0, int nE) {
           if (dA && tid < nE) dA[p0 + tid] = sd[tid];

@@ -71,9 +71,18 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
         const Part &P = pr->part[k];
         int as, ae;
         a_row(P, i, as, ae);
-        for (int p = as; p < ae; ++p) {
-          int r = a_entry_row(P, i, p);
-          key += gp(P.brp)[r + 1] - gp(P.brp)[r];
+        const SPG_GLOBAL int32_t *brp = gp(P.brp);
+        int p = as;
+        for (; p + 4 <= ae; p += 4) {  // four independent gathers in flight
+          int r[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, i, p + u);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) key += brp[r[u] + 1] - brp[r[u]];
+        }
+        for (; p < ae; ++p) {
+          const int r = a_entry_row(P, i, p);
+          key += brp[r + 1] - brp[r];
         }
       }
       if (key == 0) cnt_zero[i] = 0;
@@ -99,45 +108,38 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   }
 }
 
-// Exclusive scan of the per-block histograms in bin-major order (one block).
+// Exclusive scan of the per-block histograms in bin-major order (one block
+// of 1024 threads): wave b owns bin b; each lane sums a contiguous range of
+// blocks, one wave scan turns the sums into range offsets, then the lane
+// writes its blocks' offsets.
 __global__ __launch_bounds__(1024) void k_binscan(int32_t *blockhist, int nblk, WsHeader *hdr) {
-  __shared__ int wsum[16];
-  __shared__ int carry;
-  const int tid = threadIdx.x;
-  int base_all = 0;
-  for (int b = 0; b < kNB; ++b) {
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < nblk; c0 += 1024) {
-      int idx = c0 + tid;
-      int v = idx < nblk ? blockhist[(int64_t)idx * kNB + b] : 0;
-      // inclusive wave scan
-      int x = v;
-      for (int off = 1; off < kWave; off <<= 1) {
-        int y = __shfl_up(x, off);
-        if (lane_id() >= off) x += y;
-      }
-      if (lane_id() == kWave - 1) wsum[tid / kWave] = x;
-      __syncthreads();
-      int wpre = 0, tot = 0;
-      for (int w = 0; w < 16; ++w) {
-        if (w < tid / kWave) wpre += wsum[w];
-        tot += wsum[w];
-      }
-      int excl = carry + wpre + x - v;
-      if (idx < nblk) blockhist[(int64_t)idx * kNB + b] = base_all + excl;
-      __syncthreads();
-      if (tid == 0) carry += tot;
-      __syncthreads();
-    }
-    if (tid == 0) {
-      hdr->bin_count[b] = carry;
-      hdr->bin_start[b] = base_all;
-    }
-    base_all += carry;
-    __syncthreads();
+  __shared__ int bintot[kNB];
+  const int b = threadIdx.x / kWave;   // 16 waves, one per bin
+  const int lane = lane_id();
+  const int per = (nblk + kWave - 1) / kWave;
+  const int lo = lane * per, hi = min(nblk, lo + per);
+  int sum = 0;
+  for (int k = lo; k < hi; ++k) sum += blockhist[(int64_t)k * kNB + b];
+  int x = sum;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
   }
-  if (tid == 0) hdr->bin_start[kNB] = base_all;
+  if (lane == kWave - 1) bintot[b] = x;
+  __syncthreads();
+  int base = 0;
+  for (int bb = 0; bb < b; ++bb) base += bintot[bb];
+  int run = base + x - sum;
+  for (int k = lo; k < hi; ++k) {
+    const int v = blockhist[(int64_t)k * kNB + b];
+    blockhist[(int64_t)k * kNB + b] = run;
+    run += v;
+  }
+  if (lane == 0) {
+    hdr->bin_count[b] = bintot[b];
+    hdr->bin_start[b] = base;
+    if (b == kNB - 1) hdr->bin_start[kNB] = base + bintot[b];
+  }
 }
 
 // Stable scatter of row ids into the per-bin lists.

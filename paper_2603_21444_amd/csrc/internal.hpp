@@ -74,6 +74,16 @@ hipError_t configure_mcl_lds(size_t lds_max);
 size_t mcl_lds_bytes(int b, int G);
 int num_table_slots(int b, int G);
 
+// One-row-per-wave pipelined kernels (bins whose rows use 64 lanes).
+size_t sym_wave_lds_bytes(int b);
+size_t num_wave_lds_bytes(int b, size_t vbytes, bool pack);
+void launch_sym_wave(const Problem *dpr, const int32_t *rows, const WsHeader *hdr, int bin,
+                     int lS, int count, int32_t *cnt, hipStream_t st);
+void launch_num_wave(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin, int lS,
+                     int count, uint32_t mul, int maxwin, bool pack, const int32_t *crp,
+                     int32_t *ccol, void *cval, bool f64, int32_t *fb, hipStream_t st);
+hipError_t configure_wave_lds(size_t lds_max);
+
 // LDS bytes of one block of the symbolic / numeric kernel of bin b with G
 // lanes per row.
 size_t sym_lds_bytes(int b, int G);

@@ -40,6 +40,58 @@ struct MGeom {
   static constexpr int R = WG / G;
 };
 
+// Batched insert of the expansion products (first probes of all N issued
+// together).  Wave groups store the value of a column's first insert and add
+// repeats after a wave fence (LDS float atomics are slow), so their value
+// table needs no clearing; block groups add atomically into a cleared table.
+template <bool PLAIN>
+struct MclInsert {
+  int *key;
+  float *val;
+  int *flag;
+  uint32_t mul;
+  int maxwin;
+  template <int N>
+  __device__ __forceinline__ void batch(const int (&col)[N], const float (&v)[N]) {
+    int h[N], old[N];
+    bool ok[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      h[u] = (int)mono_slot((uint32_t)col[u], mul);
+      old[u] = col[u] >= 0 ? atomicCAS(&key[h[u]], kEmpty, (int)((uint32_t)col[u] | 0x80000000u))
+                           : kEmpty;
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      ok[u] = col[u] >= 0;
+      int d = 0;
+      while (ok[u] && old[u] != kEmpty && (int)((uint32_t)old[u] & 0xffffffu) != col[u]) {
+        if (d == maxwin) {  // the heavy kernel redoes this row
+          *flag = 1;
+          ok[u] = false;
+          break;
+        }
+        ++d;
+        ++h[u];
+        old[u] = atomicCAS(&key[h[u]], kEmpty, (int)((uint32_t)col[u] | 0x80000000u));
+      }
+    }
+    if (PLAIN) {
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (ok[u] && old[u] == kEmpty) val[h[u]] = v[u];
+      group_sync<false>();
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (ok[u] && old[u] != kEmpty) lds_add(&val[h[u]], v[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (ok[u]) lds_add(&val[h[u]], v[u]);
+    }
+  }
+};
+
 // LDS rows.  Key words pack (col | (128 + counter) << 24), n <= 2^24.
 template <int G>
 __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
@@ -73,25 +125,12 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
     if (G >= kWave) i = __builtin_amdgcn_readfirstlane(i);
     int4 *k4 = reinterpret_cast<int4 *>(key);
     for (int s = l; s < TT / 4; s += G) k4[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
-    for (int s = l; s < TT; s += G) val[s] = 0.f;
+    if (BLOCK)
+      for (int s = l; s < TT; s += G) val[s] = 0.f;
     if (l == 0) rowflag[rslot] = 0;
     group_sync<BLOCK>();
     // 1. expansion E = X X (accumulate row i)
-    auto fins = each_product([&](int col, float v) {
-          int h = (int)mono_slot((uint32_t)col, mul);
-          int d = 0;
-          int old = atomicCAS(&key[h], kEmpty, (int)((uint32_t)col | 0x80000000u));
-          while (old != kEmpty && (int)((uint32_t)old & 0xffffffu) != col) {
-            if (d == maxwin) {
-              rowflag[rslot] = 1;
-              return;
-            }
-            ++d;
-            ++h;
-            old = atomicCAS(&key[h], kEmpty, (int)((uint32_t)col | 0x80000000u));
-          }
-          lds_add(&val[h], v);
-        });
+    MclInsert<!BLOCK> fins{key, val, rowflag + rslot, mul, maxwin};
     for_each_product<BLOCK, true, G, kMclUnroll, float>(pr, i, true, l, lS, st, fins);
     group_sync<BLOCK>();
     if (rowflag[rslot]) {  // redone by the heavy kernel

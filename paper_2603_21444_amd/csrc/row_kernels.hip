@@ -130,12 +130,6 @@ __global__ __launch_bounds__(Geom<G>::WG) void k_sym_rows(const Problem *__restr
 // PACK (n <= 2^24): the counter lives in the top byte of the key word
 // (biased by 128; it stays within [-2*kTail, 2*kTail]), so the table is one
 // int array plus the values.
-template <bool PACK>
-struct KeyCode {
-  __device__ static int make(int col) { return PACK ? (int)((uint32_t)col | 0x80000000u) : col; }
-  __device__ static int col(int w) { return PACK ? (int)((uint32_t)w & 0xffffffu) : w; }
-  __device__ static int adj(int w) { return PACK ? (int)((uint32_t)w >> 24) - 128 : 0; }
-};
 
 template <typename VT, bool PACK, bool PLAIN>
 struct NumInsert {
@@ -589,6 +583,10 @@ hipError_t launch_symbolic_bins(const Problem *dpr, const BinPlan &bp, const WsL
   for (int b = 1; b <= bp.maxbin; ++b) {
     if (bp.known && bp.count[b] == 0) continue;
     int G = bp.lanes[b];
+    if (G == kWave && sym_wave_lds_bytes(b) <= D.lds_per_block) {
+      launch_sym_wave(dpr, rows, hdr, b, sub_log2(bp, b, G), bins_count(bp, b, b), cnt, st);
+      continue;
+    }
     while (G < 1024 && sym_lds_bytes(b, G) > D.lds_per_block) G *= 2;  // fewer rows per block
     const int WG = wg_for(G);
     const int R = WG / G;
@@ -664,6 +662,12 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
   for (int b = 1; b <= bp.maxbin; ++b) {
     if (bp.known && bp.count[b] == 0) continue;
     int G = bp.lanes[b];
+    if (G == kWave && num_wave_lds_bytes(b, sizeof(VT), pack) <= D.lds_per_block) {
+      launch_num_wave(dpr, rows, hdr, b, sub_log2(bp, b, G), bins_count(bp, b, b),
+                      mono_mul(bin_slots(b), bp.n), maxwin, pack, crp, ccol, cval,
+                      sizeof(VT) == 8, fb, st);
+      continue;
+    }
     while (G < 1024 && num_lds_bytes(b, G, sizeof(VT), pack) > D.lds_per_block) G *= 2;
     const int WG = wg_for(G);
     const int R = WG / G;

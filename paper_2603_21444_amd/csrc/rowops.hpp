@@ -105,6 +105,15 @@ __device__ __forceinline__ unsigned long long group_max_u64(unsigned long long v
   return t;
 }
 
+// Key word of the numeric tables.  PACK (n <= 2^24): the column in the low
+// 24 bits and a rank counter biased by 128 in the top byte.
+template <bool PACK>
+struct KeyCode {
+  __device__ static int make(int col) { return PACK ? (int)((uint32_t)col | 0x80000000u) : col; }
+  __device__ static int col(int w) { return PACK ? (int)((uint32_t)w & 0xffffffu) : w; }
+  __device__ static int adj(int w) { return PACK ? (int)((uint32_t)w >> 24) - 128 : 0; }
+};
+
 // Staging area of one group in LDS: one A entry per lane of a chunk.
 template <typename VT>
 struct Stage {

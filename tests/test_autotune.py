@@ -1,0 +1,71 @@
+"""Autotuner: candidates accepted by the library, cache round trip, and (GPU)
+a tuned plan gives the same product as the default one."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2603_21444_amd import binding
+from paper_2603_21444_amd import autotune
+
+
+def test_every_candidate_is_accepted_by_the_library():
+    p = binding.Plan()
+    for b, cands in autotune.CANDIDATES.items():
+        for lanes, sub in cands:
+            t = binding.default_tuning()
+            t.lanes[b], t.sub[b] = lanes, sub
+            p.set_tuning(t)  # raises SpgError when rejected
+
+
+def test_candidates_cover_the_default():
+    # the library caps lanes-per-entry at lanes-per-row
+    t = binding.default_tuning()
+    for b, cands in autotune.CANDIDATES.items():
+        assert (t.lanes[b], min(t.sub[b], t.lanes[b])) in cands, b
+
+
+def test_json_round_trip():
+    t = binding.default_tuning()
+    t.lanes[5], t.sub[5] = 32, 8
+    t.heavy_slots = 7
+    d = json.loads(json.dumps(autotune._to_json(t)))
+    u = autotune._from_json(d)
+    assert list(u.lanes) == list(t.lanes)
+    assert list(u.sub) == list(t.sub)
+    assert u.heavy_slots == 7 and u.max_window == t.max_window
+
+
+def test_cache_key_separates_workloads():
+    class M:
+        def __init__(self, shape):
+            self.shape = shape
+    a, b = [M((100, 50))], [M((50, 70))]
+    k1 = autotune._key(a, b, "float32", [0, 10, 1000] + [0] * 13)
+    k2 = autotune._key(a, b, "float64", [0, 10, 1000] + [0] * 13)
+    k3 = autotune._key(a, b, "float32", [0, 10, 3000] + [0] * 13)
+    k4 = autotune._key(a, b, "float32", [0, 11, 1100] + [0] * 13)
+    assert len({k1, k2, k3}) == 3
+    assert k1 == k4  # same rounded histogram
+
+
+@pytest.mark.gpu
+def test_tuned_plan_matches_default(tmp_path):
+    import torch
+    from paper_2603_21444_amd import synth
+    import oracle
+    from helpers import assert_same_csr
+    A = synth.varnnz_csr(3000, 4000, 1, 60, 41, np.float64, "u01", stream=0)
+    B = synth.varnnz_csr(4000, 5000, 1, 60, 41, np.float64, "u01", stream=1)
+    dA, dB = binding.to_device(A), binding.to_device(B)
+    t = autotune.tune([dA], [dB], reps=1, cache_path=str(tmp_path / "t.json"), share=0.0)
+    assert (tmp_path / "t.json").exists()
+    t2 = autotune.tune([dA], [dB], reps=1, cache_path=str(tmp_path / "t.json"))
+    assert list(t2.lanes) == list(t.lanes) and list(t2.sub) == list(t.sub)
+    plan = binding.Plan(tuning=t)
+    rp, nnz = plan.symbolic([dA], [dB])
+    col, vals = plan.numeric([dA], [dB], rp, nnz)
+    torch.cuda.synchronize()
+    got = binding.DeviceCSR((3000, 5000), rp, col, vals).to_host()
+    ref, S = oracle.spgemm(A, B, with_abs=True)
+    assert_same_csr(got, ref, S, np.float64, what="tuned plan")
