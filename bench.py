@@ -234,14 +234,17 @@ def bench_mcl(args):
 def traffic_from_profile(kernel_src_hash):
     """HBM bytes per launch of the numeric kernel from the committed counter
     summary, if it was taken from the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "numeric_uniform2p20_fp32_traffic.json")
+    path = os.path.join(ROOT, "profiles", "numeric_uniform2p20_fp32_traffic.txt")
     if not os.path.exists(path):
         return None
+    fields = {}
     with open(path) as f:
-        d = json.load(f)
-    if d.get("source_sha256") != kernel_src_hash:
+        for line in f:
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != kernel_src_hash:
         return None
-    return d.get("traffic_bytes")
+    return int(fields["traffic_bytes"])
 
 
 def kernel_source_hash():
