@@ -513,13 +513,15 @@ int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg
 
 static void mcl_layout(int32_t n, int32_t topk, WsLayout &L, size_t &pcol, size_t &pval,
                        size_t &total, int &cap) {
-  L = ws_layout(n, n, default_heavy_slots(n));
+  L = ws_layout(n, n, 0);
   cap = topk < n ? topk : n;
   if (cap < 1) cap = 1;
   const size_t pad = (size_t)std::max(n, 1) * (size_t)cap;
   pcol = (L.total + 255) & ~(size_t)255;
   pval = (pcol + 4 * pad + 255) & ~(size_t)255;
-  total = pval + 4 * pad;
+  L.mcl_rabs = (pval + 4 * pad + 255) & ~(size_t)255;
+  L.mcl_slots = (L.mcl_rabs + 8 * (size_t)std::max(n, 1) + 255) & ~(size_t)255;
+  total = L.mcl_slots + (size_t)mcl_heavy_slots(n) * mcl_slot_bytes(n);
 }
 
 int spgemm_mcl_workspace_size(int32_t n, int32_t topk, size_t *bytes) {
@@ -538,7 +540,7 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
   if (!plan || !X || !Y_row_ptr) return SPG_ERR_ARG;
   if (X->nrows != X->ncols) return SPG_ERR_SHAPE;
   if (r < 1 || r > 8 || topk < 1 || !(prune >= 0.f) || !(prune < 1e30f)) return SPG_ERR_ARG;
-  if (X->ncols > kLdsBitmapCols) return SPG_ERR_UNSUPPORTED;  // heavy rows keep a bitmap in LDS
+  if (X->ncols > kMclMaxCols) return SPG_ERR_UNSUPPORTED;  // 24-bit columns in the LDS tables
   if (!Y_nnz_host && capacity < 0) return SPG_ERR_ARG;
   if (X->nnz > 0 && (!X->col_idx || !X->vals)) return SPG_ERR_ARG;
   const int n = X->nrows;

@@ -15,6 +15,7 @@ constexpr int kHeavyBin = 12;       // rows beyond every LDS table
 constexpr int kMaxLdsBin = 11;      // largest LDS bin index
 constexpr int kTail = 32;           // slots after a table: a probe walks at most kTail past it
 constexpr int kLdsBitmapCols = 1 << 20;  // columns a heavy row can mark in LDS (128 KiB)
+constexpr int kMclMaxCols = 1 << 24;     // MCL keys hold the column in 24 bits
 
 // Status bits raised by kernels in the workspace header.
 constexpr int kStatOverflow = 1;

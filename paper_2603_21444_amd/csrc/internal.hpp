@@ -26,7 +26,19 @@ const DevInfo &dev_info();
 struct WsLayout {
   size_t problem, binid, rows, fbrows, blockhist, scanpart, heavyacc, heavymap, total;
   int heavy_slots;
+  size_t mcl_rabs = 0, mcl_slots = 0;  // MCL only: row sums of |x|, heavy-row slots
 };
+
+// MCL heavy rows: per-slot scratch (candidate list + entry cursors, 16 B per
+// column) and the number of slots (concurrent heavy rows, at most 512, at
+// most 4 GiB of scratch).
+inline size_t mcl_slot_bytes(int64_t n) {
+  return ((size_t)16 * (size_t)(n > 0 ? n : 1) + 255) & ~(size_t)255;
+}
+inline int mcl_heavy_slots(int64_t n) {
+  const int64_t s = ((int64_t)4 << 30) / (int64_t)mcl_slot_bytes(n);
+  return (int)(s < 1 ? 1 : (s > 512 ? 512 : s));
+}
 
 WsLayout ws_layout(int64_t m, int64_t n, int heavy_slots);
 int default_heavy_slots(int64_t n);

@@ -8,10 +8,9 @@
 //
 // Rows whose products fit an LDS table use the numeric kernel's
 // order-preserving hash (rank = occupied slots before + inversion counter)
-// and run the whole epilogue in LDS; rows beyond the tables use a column
-// bitmap and the heavy slot's dense accumulator, whose bitmap walk is in
-// column order.  Kept entries are flagged by clearing the sign of their
-// value slot (LDS rows) or by clearing their bitmap bit (heavy rows).
+// and run the whole epilogue in LDS; kept entries are flagged by clearing
+// the sign of their value slot.  Rows beyond the tables are swept in column
+// panels (k_mcl_panel below).
 #include <vector>
 
 #include "internal.hpp"
@@ -268,174 +267,379 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
   }
 }
 
-// Heavy rows: bitmap (LDS, n <= 2^20) + the slot's dense accumulator.  The
-// rows come from the bins above the LDS tables and from the LDS kernel's
-// hand-over list (probe longer than the window).
-__global__ __launch_bounds__(1024) void k_mcl_heavy(
+// ---------------------------------------------------------------------------
+// Heavy rows: column panels with fixed-point accumulators in LDS.
+//
+// A heavy row (more products than an LDS table holds, or handed over by the
+// LDS kernel) is swept in panels of kPanel consecutive columns.  Each of the
+// block's 1024 threads owns one entry a_ik of X row i and walks B row k
+// (sorted, as X is canonical) with a cursor held in registers, kPB elements
+// per load round; the round that ends a panel already holds the first
+// elements of the next one.  A product a_ik * b_kj (exact in FP64) is scaled
+// by 2^s and rounded to an int64 that is added into the panel's LDS slot with
+// an integer atomic: integer LDS atomics are far cheaper than float ones on
+// this chip, and the sum no longer depends on the order of the adds.  The
+// scale is chosen per row from sum_k |a_ik| * sum_j |b_kj| (row_abs below) so
+// that no partial sum can overflow; the rounding error of an entry is at most
+// (terms) * 2^-62 of that bound, far below the FP32 rounding of the result.
+//
+// After a panel, its present columns are inflated (p = v^r) and p is summed
+// into the row's running sum.  A column can only survive the prune if
+// p >= prune * (final sum) >= prune * (sum of the panels before), so only
+// such candidates are appended, in column order, to the row's list in the
+// slot scratch (capacity n).  At the end the list is filtered with the exact
+// test on p / sum, the top-k threshold is found by bisection on the float
+// bit patterns, ties go to the smaller columns (list order), and the result is
+// renormalised and written in column order.
+constexpr int kPanel = 8192;  // columns per panel: 64 KiB of int64 in LDS
+constexpr int kPT = 1024;     // threads of a heavy block
+constexpr int kPB = 8;        // B elements per entry per load round
+static_assert(kPanel == kPT * 8, "the epilogue gives each thread 8 columns");
+
+struct PanelRed {
+  double s;
+  int total, excl, mn;
+  unsigned long long best;
+};
+
+// Block-wide sum (double), inclusive/exclusive count scan, min and max in one
+// barrier.  The caller synchronises before the shared arrays are reused.
+__device__ __forceinline__ PanelRed panel_reduce(double s, int c, int mn, unsigned long long best,
+                                                 double *rs, int *rc, int *rm,
+                                                 unsigned long long *rb) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  int x = c;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off);
+    const int m2 = __shfl_xor(mn, off);
+    mn = m2 < mn ? m2 : mn;
+    const unsigned long long b2 = __shfl_xor(best, off);
+    best = b2 > best ? b2 : best;
+  }
+  if (lane == kWave - 1) rc[w] = x;
+  if (lane == 0) {
+    rs[w] = s;
+    rm[w] = mn;
+    rb[w] = best;
+  }
+  __syncthreads();
+  // lane l (mod 16) picks up wave l's partials; a butterfly over 16 lanes
+  // gives every lane the same totals (IEEE addition is commutative).
+  constexpr int NW = kPT / kWave;
+  static_assert(NW == 16, "one partial per lane of a 16-lane segment");
+  const int l16 = lane & (NW - 1);
+  double ts = rs[l16];
+  int tt = rc[l16];
+  int tp = l16 < w ? tt : 0;
+  int tm = rm[l16];
+  unsigned long long tb = rb[l16];
+#pragma unroll
+  for (int off = NW / 2; off > 0; off >>= 1) {
+    ts += __shfl_xor(ts, off, NW);
+    tt += __shfl_xor(tt, off, NW);
+    tp += __shfl_xor(tp, off, NW);
+    const int m2 = __shfl_xor(tm, off, NW);
+    tm = m2 < tm ? m2 : tm;
+    const unsigned long long b2 = __shfl_xor(tb, off, NW);
+    tb = b2 > tb ? b2 : tb;
+  }
+  return PanelRed{ts, tt, tp + x - c, tm, tb};
+}
+
+template <int NB>
+__device__ __forceinline__ void load_round(const SPG_GLOBAL int32_t *bcol,
+                                           const SPG_GLOBAL float *bval, int cur, int end,
+                                           int (&bc)[NB], float (&bv)[NB]) {
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const bool in = cur + u < end;
+    bc[u] = in ? bcol[cur + u] : INT32_MAX;
+    bv[u] = in ? bval[cur + u] : 0.f;
+  }
+}
+
+// Adds the products of one entry that fall in [plo, plo + kPanel); on return
+// bc/bv hold the entry's elements from the new cursor on.
+template <int NB>
+__device__ __forceinline__ void panel_entry(const SPG_GLOBAL int32_t *bcol,
+                                            const SPG_GLOBAL float *bval, int &cur, int end,
+                                            double a, double sigma, int plo, uint32_t width,
+                                            unsigned long long *pacc, uint32_t *pbm,
+                                            int (&bc)[NB], float (&bv)[NB]) {
+  const int phi = plo + kPanel;
+  while (bc[0] < phi) {
+    int k = 0;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (k == u && bc[u] < phi) {
+        k = u + 1;
+        const uint32_t cl = (uint32_t)(bc[u] - plo);
+        if (cl < width) {  // columns outside [0, n) are skipped
+          const long long q = __double2ll_rn(a * (double)bv[u] * sigma);
+          atomicAdd(&pacc[cl], (unsigned long long)q);
+          atomicOr(&pbm[cl >> 5], 1u << (cl & 31));
+        }
+      }
+    }
+    cur += k;
+    load_round(bcol, bval, cur, end, bc, bv);
+  }
+}
+
+__global__ __launch_bounds__(kPT) void k_mcl_panel(
     const Problem *__restrict__ pr, const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
-    int blo, int lS, int r, float prune, int topk, int cap, float *gacc,
-    const int32_t *__restrict__ fb_rows, int32_t *__restrict__ ycol, float *__restrict__ yval,
-    int32_t *__restrict__ ycnt) {
-  extern __shared__ __align__(16) uint32_t map[];
-  __shared__ int sb[1024], sl[1024];
-  __shared__ float sa[1024];
-  __shared__ float redf[16];
-  __shared__ int redi[16];
-  __shared__ unsigned long long redu[16];
+    int blo, int r, float prune, int topk, int cap, const double *__restrict__ rabs,
+    char *__restrict__ scratch, size_t slot_bytes, const int32_t *__restrict__ fb_rows,
+    int32_t *__restrict__ ycol, float *__restrict__ yval, int32_t *__restrict__ ycnt) {
+  extern __shared__ __align__(16) unsigned long long pacc[];
+  uint32_t *pbm = reinterpret_cast<uint32_t *>(pacc + kPanel);
+  __shared__ double rs[kPT / kWave];
+  __shared__ int rc[kPT / kWave], rm[kPT / kWave];
+  __shared__ unsigned long long rb[kPT / kWave];
   const int n = pr->n;
-  const int nw = (n + 31) >> 5;
-  float *acc = gacc + (size_t)blockIdx.x * n;
-  if (hdr->status) return;
+  const int tid = threadIdx.x;
+  char *sp = scratch + (size_t)blockIdx.x * slot_bytes;
+  int32_t *lcol = reinterpret_cast<int32_t *>(sp);
+  float *lval = reinterpret_cast<float *>(sp + (size_t)4 * n);
+  int32_t *ecur = reinterpret_cast<int32_t *>(sp + (size_t)8 * n);
+  int32_t *eend = reinterpret_cast<int32_t *>(sp + (size_t)12 * n);
+  __shared__ int stat0;
+  if (tid == 0) stat0 = hdr->status;
+  __syncthreads();
+  if (stat0) return;
+  const Part &P = pr->part[0];
+  const SPG_GLOBAL int32_t *bcol = gp(P.bcol);
+  const SPG_GLOBAL float *bval = gp(static_cast<const float *>(P.bval));
   const int start = hdr->bin_start[blo];
   const int nheavy = hdr->bin_start[kHeavyBin + 1] - start;
   const int count = nheavy + hdr->fallback_count;
-  const int tid = threadIdx.x;
-  Stage<float> st{sb, sl, sa};
+  for (int s = tid; s < kPanel; s += kPT) pacc[s] = 0ull;
+  for (int s = tid; s < kPanel / 32; s += kPT) pbm[s] = 0u;
+  __syncthreads();
+  const bool even = (r & 1) == 0;
   for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
     const int i = ri < nheavy ? rows[start + ri] : fb_rows[ri - nheavy];
-    for (int w = tid; w < nw; w += 1024) map[w] = 0u;
-    __syncthreads();
-    auto fmark = each_product([&](int col, float) {
-      const uint32_t bit = 1u << (col & 31);
-      if (!(atomicOr(&map[col >> 5], bit) & bit)) acc[col] = 0.f;
-    });
-    for_each_product<true, false, 1024, kMclUnroll, float>(pr, i, true, tid, lS, st, fmark);
-    __threadfence();
-    __syncthreads();
-    auto fadd = each_product([&](int col, float v) { global_add(&acc[col], v); });
-    for_each_product<true, true, 1024, kMclUnroll, float>(pr, i, true, tid, lS, st, fadd);
-    __threadfence();
-    __syncthreads();
-    // inflation + sum
-    float part = 0.f;
-    for (int w = tid; w < nw; w += 1024) {
-      uint32_t b = map[w];
-      while (b) {
-        const int col = (w << 5) + __ffs(b) - 1;
-        b &= b - 1;
-        const float p = ipow(acc[col], r);
-        acc[col] = p;
-        part += p;
+    int as, ae;
+    a_row(P, i, as, ae);
+    const int nA = ae - as;
+    if (nA > n) {  // more entries than columns: a repeated column index
+      if (tid == 0) atomicOr(&hdr->status, kStatInvalid);
+      break;
+    }
+    // entries: the first kPT in registers, the rest in the slot scratch
+    int cur = 0, end = 0;
+    double a0 = 0.0, sb = 0.0;
+    int mn = INT32_MAX;
+    for (int e = tid; e < nA; e += kPT) {
+      const int k = gp(P.acol)[as + e];
+      const float av = gp(static_cast<const float *>(P.aval))[as + e];
+      const int b0 = gp(P.brp)[k], b1 = gp(P.brp)[k + 1];
+      sb += fabs((double)av) * rabs[k];
+      if (e == tid) {
+        cur = b0;
+        end = b1;
+        a0 = av;
+      } else {
+        ecur[e] = b0;
+        eend[e] = b1;
+        if (b0 < b1) mn = min(mn, bcol[b0]);
       }
     }
-    const float S = group_sum<true, 1024>(part, redf);
-    // normalise, prune (clear the bit of a dropped entry), largest entry
-    int kept = 0;
-    unsigned long long best = 0;
-    for (int w = tid; w < nw; w += 1024) {
-      uint32_t b = map[w], keepbits = map[w];
-      while (b) {
-        const int j = __ffs(b) - 1;
-        const int col = (w << 5) + j;
-        b &= b - 1;
-        const float v = acc[col] / S;
-        acc[col] = v;
-        const unsigned long long kk = vc_key(v, col);
-        best = kk > best ? kk : best;
-        if (v < prune) keepbits &= ~(1u << j);
-        else ++kept;
+    int bc[kPB];
+    float bv[kPB];
+    load_round(bcol, bval, cur, end, bc, bv);
+    mn = min(mn, bc[0]);
+    PanelRed R = panel_reduce(sb, 0, mn, 0ull, rs, rc, rm, rb);
+    __syncthreads();
+    // scale 2^s with 2^(62-s) > the row's bound on sum |a b|
+    double sigma = 1.0;
+    {
+      const double bound = R.s * (1.0 + 1.0 / 1048576.0);
+      if (bound > 0.0 && bound < 1e300) {
+        int ex = 0;
+        (void)frexp(bound, &ex);  // bound < 2^ex
+        ex = ex < -960 ? -960 : ex;
+        sigma = ldexp(1.0, 62 - ex);
       }
-      map[w] = keepbits;
     }
-    const int nkept = group_sum<true, 1024>(kept, redi);
-    if (nkept > topk) {
-      uint32_t lo = 0, hi = 0x7f800000u;
+    int mnext = R.mn;
+    double scum = 0.0;
+    int nc = 0;
+    unsigned long long best = 0ull;
+    while (mnext < n) {
+      const int plo = mnext & ~(kPanel - 1);
+      const uint32_t width = plo < 0 ? 0u : (uint32_t)min(kPanel, n - plo);
+      panel_entry(bcol, bval, cur, end, a0, sigma, plo, width, pacc, pbm, bc, bv);
+      int tmn = bc[0];
+      for (int e = tid + kPT; e < nA; e += kPT) {
+        int c2 = ecur[e];
+        const int e2 = eend[e];
+        int bc2[2];
+        float bv2[2];
+        load_round(bcol, bval, c2, e2, bc2, bv2);
+        panel_entry(bcol, bval, c2, e2, (double)gp(static_cast<const float *>(P.aval))[as + e],
+                    sigma, plo, width, pacc, pbm, bc2, bv2);
+        ecur[e] = c2;
+        tmn = min(tmn, bc2[0]);
+      }
+      __syncthreads();
+      // epilogue of the panel: thread tid owns columns plo + 8 tid .. + 7
+      const double thr = even ? (double)prune * scum * (1.0 - 1.0 / 1024.0) : -HUGE_VAL;
+      const uint32_t bits = (pbm[tid >> 2] >> ((tid & 3) * 8)) & 0xffu;
+      double ps = 0.0;
+      int cnt = 0;
+      for (uint32_t b = bits; b; b &= b - 1) {
+        const int cl = tid * 8 + __ffs(b) - 1;
+        const float pw = ipow((float)((double)(long long)pacc[cl] / sigma), r);
+        ps += (double)pw;
+        const unsigned long long key = vc_key(pw, plo + cl);
+        best = key > best ? key : best;
+        cnt += (double)pw >= thr ? 1 : 0;
+      }
+      R = panel_reduce(ps, cnt, tmn, 0ull, rs, rc, rm, rb);
+      int o = nc + R.excl;
+      for (uint32_t b = bits; b; b &= b - 1) {
+        const int cl = tid * 8 + __ffs(b) - 1;
+        const float pw = ipow((float)((double)(long long)pacc[cl] / sigma), r);
+        pacc[cl] = 0ull;
+        if ((double)pw >= thr) {
+          lcol[o] = plo + cl;
+          lval[o] = pw;
+          ++o;
+        }
+      }
+      if ((tid & 3) == 0) pbm[tid >> 2] = 0u;
+      scum += R.s;
+      nc += R.total;
+      mnext = R.mn;
+      __syncthreads();
+    }
+    // exact prune test on p / sum, compacting the list in place
+    const float S = (float)scum;
+    int nk = 0;
+    for (int c0 = 0; c0 < nc; c0 += kPT) {
+      const int idx = c0 + tid;
+      int col = 0;
+      float q = 0.f;
+      bool keep = false;
+      if (idx < nc) {
+        col = lcol[idx];
+        q = lval[idx] / S;
+        keep = !(q < prune);
+      }
+      R = panel_reduce(0.0, keep ? 1 : 0, INT32_MAX, best, rs, rc, rm, rb);
+      if (keep) {
+        lcol[nk + R.excl] = col;
+        lval[nk + R.excl] = q + 0.f;
+      }
+      nk += R.total;
+      __syncthreads();
+    }
+    R = panel_reduce(0.0, 0, INT32_MAX, best, rs, rc, rm, rb);
+    const unsigned long long rowbest = R.best;
+    __syncthreads();
+    // top-k: largest threshold tau with at least topk kept values >= tau
+    uint32_t tau = 0u;
+    int need = nk;
+    if (nk > topk) {
+      uint32_t lo = 0u, hi = 0x7f800000u;
       while (lo < hi) {
         const uint32_t mid = lo + (hi - lo + 1) / 2;
         int cc = 0;
-        for (int w = tid; w < nw; w += 1024) {
-          uint32_t b = map[w];
-          while (b) {
-            const int col = (w << 5) + __ffs(b) - 1;
-            b &= b - 1;
-            cc += __float_as_uint(acc[col]) >= mid ? 1 : 0;
-          }
-        }
-        if (group_sum<true, 1024>(cc, redi) >= topk) lo = mid;
+        for (int idx = tid; idx < nk; idx += kPT) cc += __float_as_uint(lval[idx]) >= mid ? 1 : 0;
+        R = panel_reduce(0.0, cc, INT32_MAX, 0ull, rs, rc, rm, rb);
+        __syncthreads();
+        if (R.total >= topk) lo = mid;
         else hi = mid - 1;
       }
+      tau = lo;
       int gt = 0;
-      for (int w = tid; w < nw; w += 1024) {
-        uint32_t b = map[w];
-        while (b) {
-          const int col = (w << 5) + __ffs(b) - 1;
-          b &= b - 1;
-          gt += __float_as_uint(acc[col]) > lo ? 1 : 0;
+      for (int idx = tid; idx < nk; idx += kPT) gt += __float_as_uint(lval[idx]) > tau ? 1 : 0;
+      R = panel_reduce(0.0, gt, INT32_MAX, 0ull, rs, rc, rm, rb);
+      __syncthreads();
+      need = topk - R.total;  // ties at tau to keep, in column order
+    }
+    // renormalising sum of the selected entries, then the ordered write
+    const bool select_all = nk <= topk;
+    double s2 = 0.0;
+    {
+      int seen = 0;
+      for (int c0 = 0; c0 < nk; c0 += kPT) {
+        const int idx = c0 + tid;
+        float q = 0.f;
+        int tie = 0;
+        if (idx < nk) {
+          q = lval[idx];
+          tie = (!select_all && __float_as_uint(q) == tau) ? 1 : 0;
         }
-      }
-      const int need = topk - group_sum<true, 1024>(gt, redi);
-      // ties at tau keep the smallest columns: prefix count in column order
-      int done = 0;
-      for (int w0 = 0; w0 < nw; w0 += 1024) {
-        const int w = w0 + tid;
-        uint32_t bits = w < nw ? map[w] : 0u;
-        int eq = 0;
-        uint32_t b = bits;
-        while (b) {
-          const int col = (w << 5) + __ffs(b) - 1;
-          b &= b - 1;
-          eq += __float_as_uint(acc[col]) == lo ? 1 : 0;
-        }
-        int tot;
-        int before = done + group_excl_scan<true, 1024>(eq, tid, redi, tot);
-        b = bits;
-        uint32_t keepbits = bits;
-        while (b) {
-          const int j = __ffs(b) - 1;
-          const int col = (w << 5) + j;
-          b &= b - 1;
-          const uint32_t vb = __float_as_uint(acc[col]);
-          bool keep = vb > lo;
-          if (vb == lo) keep = (before++ < need);
-          if (!keep) keepbits &= ~(1u << j);
-        }
-        if (w < nw) map[w] = keepbits;
-        done += tot;
+        R = panel_reduce(0.0, tie, INT32_MAX, 0ull, rs, rc, rm, rb);
+        bool sel = false;
+        if (idx < nk)
+          sel = select_all || __float_as_uint(q) > tau || (tie && seen + R.excl < need);
+        seen += R.total;
+        if (idx < nk && !sel) lval[idx] = -1.f;  // dropped by the top-k
+        s2 += sel ? (double)q : 0.0;
+        __syncthreads();
       }
     }
+    R = panel_reduce(s2, 0, INT32_MAX, 0ull, rs, rc, rm, rb);
+    const float S2 = (float)R.s;
     __syncthreads();
-    if (nkept == 0) {
-      const unsigned long long bb = group_max_u64<true, 1024>(best, redu);
-      if (bb != 0 || true) {
-        const int bcol = (int)~(uint32_t)(bb & 0xffffffffu);
-        if (tid == 0 && bcol >= 0 && bcol < n) map[bcol >> 5] |= 1u << (bcol & 31);
-      }
-    }
-    __syncthreads();
-    float part2 = 0.f;
-    for (int w = tid; w < nw; w += 1024) {
-      uint32_t b = map[w];
-      while (b) {
-        const int col = (w << 5) + __ffs(b) - 1;
-        b &= b - 1;
-        part2 += acc[col];
-      }
-    }
-    const float S2 = group_sum<true, 1024>(part2, redf);
-    // write in column order
-    int pre = 0;
     SPG_GLOBAL int32_t *cb = gpw(ycol) + (size_t)i * cap;
-    SPG_GLOBAL float *vb2 = gpw(yval) + (size_t)i * cap;
-    for (int w0 = 0; w0 < nw; w0 += 1024) {
-      const int w = w0 + tid;
-      const uint32_t bits = w < nw ? map[w] : 0u;
-      int tot;
-      int o = pre + group_excl_scan<true, 1024>(__popc(bits), tid, redi, tot);
-      uint32_t b = bits;
-      while (b) {
-        const int col = (w << 5) + __ffs(b) - 1;
-        b &= b - 1;
-        if (o < cap) {
-          cb[o] = col;
-          vb2[o] = acc[col] / S2;
+    SPG_GLOBAL float *vb = gpw(yval) + (size_t)i * cap;
+    int outn = 0;
+    if (nk == 0) {
+      if (rowbest != 0ull) {  // emptied row: keep its largest entry
+        if (tid == 0) {
+          const float q = __uint_as_float((uint32_t)(rowbest >> 32)) / S;
+          cb[0] = (int)~(uint32_t)(rowbest & 0xffffffffu);
+          vb[0] = q / q;
         }
-        ++o;
+        outn = 1;
       }
-      pre += tot;
+    } else {
+      for (int c0 = 0; c0 < nk; c0 += kPT) {
+        const int idx = c0 + tid;
+        const bool sel = idx < nk && !(lval[idx] < 0.f);
+        R = panel_reduce(0.0, sel ? 1 : 0, INT32_MAX, 0ull, rs, rc, rm, rb);
+        const int o = outn + R.excl;
+        if (sel && o < cap) {
+          cb[o] = lcol[idx];
+          vb[o] = lval[idx] / S2;
+        }
+        outn += R.total;
+        __syncthreads();
+      }
     }
-    if (tid == 0) ycnt[i] = pre < cap ? pre : cap;
-    __threadfence();
+    if (tid == 0) ycnt[i] = outn < cap ? outn : cap;
     __syncthreads();
+  }
+}
+
+// Row sums of |x| in FP64 (the heavy kernel's fixed-point scale bound).
+__global__ __launch_bounds__(256) void k_row_abs(const Problem *__restrict__ pr,
+                                                 const WsHeader *__restrict__ hdr,
+                                                 double *__restrict__ rabs) {
+  if (hdr->status) return;
+  const Part &P = pr->part[0];
+  const int n = P.kdim;
+  const int lane = lane_id();
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const SPG_GLOBAL float *bval = gp(static_cast<const float *>(P.bval));
+  for (int64_t k = wv; k < n; k += nwv) {
+    const int s = gp(P.brp)[k], e = gp(P.brp)[k + 1];
+    double t = 0.0;
+    for (int j = s + lane; j < e; j += kWave) t += fabs((double)bval[j]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0) rabs[k] = t;
   }
 }
 
@@ -516,14 +720,14 @@ hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, 
   }
   {
     // heavy bins plus rows handed over by the LDS kernels
-    const int grid = bp.heavy_slots;
-    int S = bp.sub[kHeavyBin] > 0 ? bp.sub[kHeavyBin] : 16;
-    int lS = 0;
-    while ((1 << lS) < S) ++lS;
-    const size_t lds = (size_t)((bp.n + 31) >> 5) * 4;
-    hipLaunchKernelGGL(k_mcl_heavy, dim3(grid), dim3(1024), lds, st, dpr, rows, hdr, bp.maxbin + 1,
-                       lS, r, prune, topk, cap, reinterpret_cast<float *>(ws + L.heavyacc), fb, pcol,
-                       pval, ycnt);
+    // one 1024-thread block per CU (its register use allows no second one)
+    const int grid = std::min(mcl_heavy_slots(bp.n), D.cus);
+    double *rabs = reinterpret_cast<double *>(ws + L.mcl_rabs);
+    hipLaunchKernelGGL(k_row_abs, dim3(D.cus * 8), dim3(256), 0, st, dpr, hdr, rabs);
+    const size_t lds = (size_t)kPanel * 8 + (size_t)kPanel / 8;
+    hipLaunchKernelGGL(k_mcl_panel, dim3(grid), dim3(kPT), lds, st, dpr, rows, hdr, bp.maxbin + 1,
+                       r, prune, topk, cap, rabs, ws + L.mcl_slots, mcl_slot_bytes(bp.n), fb,
+                       pcol, pval, ycnt);
   }
   return hipGetLastError();
 }
@@ -543,7 +747,7 @@ hipError_t configure_mcl_lds(size_t lds_max) {
       reinterpret_cast<const void *>(&k_mcl_rows<32>),  reinterpret_cast<const void *>(&k_mcl_rows<64>),
       reinterpret_cast<const void *>(&k_mcl_rows<128>), reinterpret_cast<const void *>(&k_mcl_rows<256>),
       reinterpret_cast<const void *>(&k_mcl_rows<512>), reinterpret_cast<const void *>(&k_mcl_rows<1024>),
-      reinterpret_cast<const void *>(&k_mcl_heavy),
+      reinterpret_cast<const void *>(&k_mcl_panel),
   };
   for (const void *k : ks) {
     hipError_t e =

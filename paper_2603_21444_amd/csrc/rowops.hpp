@@ -122,82 +122,103 @@ struct Stage {
   VT *a;     // value a_ik
 };
 
-// Hands every product (col, a_ik * b_kj) of row i to f.batch<N>(cols, vals)
-// (N products per lane at once, col < 0 = no product), so that f can issue
-// the LDS operations of N products before waiting on any of them.  The entries of an
-// A row are taken in chunks of G: lane l stages entry c0+l in LDS (one
-// coalesced read of A, one gather of B row bounds).  Then S = 2^lS lanes
-// share each entry: lane l reads position (l mod S) of the B rows of
-// entries l/S, l/S + G/S, ..., U entries at a time so that U loads are in
-// flight together, and consecutive lanes read consecutive B entries.
-// Positions beyond S (B rows longer than S) follow in a second loop.
+// Hands every product (col, a_ik * b_kj) of row i of A_k B_k (one part) to
+// f.batch<N>(cols, vals) (N products per lane at once, col < 0 = no
+// product), so that f can issue the LDS operations of N products before
+// waiting on any of them.  The entries of the A row are taken in chunks of
+// G: lane l stages entry c0+l in LDS (one coalesced read of A, one gather of
+// B row bounds).  Then S = 2^lS lanes share each entry (S grows while the
+// chunk's entries leave lanes idle: few entries with long B rows): lane l
+// reads position (l mod S) of the B rows of entries l/S, l/S + G/S, ..., U
+// entries at a time so that U loads are in flight together, and consecutive
+// lanes read consecutive B entries.  Positions beyond S (B rows longer than
+// S) follow in a second loop.
+template <bool BLOCK, bool VALUES, int G, int U, typename VT, typename F>
+__device__ __forceinline__ void part_products(const Part &P, int i, bool active, int l, int lS,
+                                              Stage<VT> st, F &f) {
+  const SPG_GLOBAL int32_t *brp = gp(P.brp);
+  const SPG_GLOBAL int32_t *bcol = gp(P.bcol);
+  const SPG_GLOBAL VT *bval = gp(static_cast<const VT *>(P.bval));
+  int as = 0, ae = 0;
+  if (active) a_row(P, i, as, ae);
+  const int nA = ae - as;
+  for (int c0 = 0; c0 < nA; c0 += G) {
+    const int e = c0 + l;
+    if (e < nA) {
+      int r;
+      VT a = VT(1);
+      if (P.a_identity) {
+        r = i;
+      } else {
+        r = gp(P.acol)[as + e];
+        if (VALUES) a = gp(static_cast<const VT *>(P.aval))[as + e];
+      }
+      const int b0 = brp[r];
+      st.b0[l] = b0;
+      st.len[l] = brp[r + 1] - b0;
+      if (VALUES) st.a[l] = a;
+    }
+    const int nE = min(G, nA - c0);
+    int lSr = lS;
+    while (lSr < 6 && (nE << (lSr + 1)) <= G) ++lSr;
+    const int S = 1 << lSr;
+    const int ES = G >> lSr;
+    const int sg = l >> lSr;
+    const int q0 = l & (S - 1);
+    group_sync<BLOCK>();
+    for (int t0 = sg; t0 < nE; t0 += ES * U) {
+      int col[U];
+      VT v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int ee = t0 + ES * u;
+        col[u] = -1;
+        v[u] = VT(0);
+        if (ee < nE && q0 < st.len[ee]) {
+          const int idx = st.b0[ee] + q0;
+          col[u] = bcol[idx];
+          if (VALUES) v[u] = st.a[ee] * bval[idx];
+        }
+      }
+      f.template batch<U>(col, v);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int ee = t0 + ES * u;
+        if (ee < nE) {
+          const int len = st.len[ee];
+          for (int q = q0 + S; q < len; q += S) {
+            const int idx = st.b0[ee] + q;
+            int c1[1] = {bcol[idx]};
+            VT v1[1] = {VALUES ? st.a[ee] * bval[idx] : VT(0)};
+            f.template batch<1>(c1, v1);
+          }
+        }
+      }
+    }
+    group_sync<BLOCK>();
+  }
+}
+
+// All products of row i of C = sum_k A_k B_k.  A row handled by a whole
+// block with K > 1 parts gives each of its waves its own parts (the parts'
+// chains of dependent loads then overlap instead of following each other);
+// the waves share the block's table and meet at one barrier at the end.
 template <bool BLOCK, bool VALUES, int G, int U, typename VT, typename F>
 __device__ __forceinline__ void for_each_product(const Problem *__restrict__ pr, int i,
                                                  bool active, int l, int lS, Stage<VT> st,
                                                  F &f) {
   const int K = pr->K;
-  const int S = 1 << lS;
-  const int ES = G >> lS;
-  const int sg = l >> lS;
-  const int q0 = l & (S - 1);
-  for (int k = 0; k < K; ++k) {
-    const Part &P = pr->part[k];
-    const SPG_GLOBAL int32_t *brp = gp(P.brp);
-    const SPG_GLOBAL int32_t *bcol = gp(P.bcol);
-    const SPG_GLOBAL VT *bval = gp(static_cast<const VT *>(P.bval));
-    int as = 0, ae = 0;
-    if (active) a_row(P, i, as, ae);
-    const int nA = ae - as;
-    for (int c0 = 0; c0 < nA; c0 += G) {
-      const int e = c0 + l;
-      if (e < nA) {
-        int r;
-        VT a = VT(1);
-        if (P.a_identity) {
-          r = i;
-        } else {
-          r = gp(P.acol)[as + e];
-          if (VALUES) a = gp(static_cast<const VT *>(P.aval))[as + e];
-        }
-        const int b0 = brp[r];
-        st.b0[l] = b0;
-        st.len[l] = brp[r + 1] - b0;
-        if (VALUES) st.a[l] = a;
-      }
-      const int nE = min(G, nA - c0);
-      group_sync<BLOCK>();
-      for (int t0 = sg; t0 < nE; t0 += ES * U) {
-        int col[U];
-        VT v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int ee = t0 + ES * u;
-          col[u] = -1;
-          v[u] = VT(0);
-          if (ee < nE && q0 < st.len[ee]) {
-            const int idx = st.b0[ee] + q0;
-            col[u] = bcol[idx];
-            if (VALUES) v[u] = st.a[ee] * bval[idx];
-          }
-        }
-        f.template batch<U>(col, v);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int ee = t0 + ES * u;
-          if (ee < nE) {
-            const int len = st.len[ee];
-            for (int q = q0 + S; q < len; q += S) {
-              const int idx = st.b0[ee] + q;
-              int c1[1] = {bcol[idx]};
-              VT v1[1] = {VALUES ? st.a[ee] * bval[idx] : VT(0)};
-              f.template batch<1>(c1, v1);
-            }
-          }
-        }
-      }
-      group_sync<BLOCK>();
-    }
+  if (BLOCK && K > 1) {
+    constexpr int NWV = G / kWave;
+    const int w = l / kWave, lw = l % kWave;
+    Stage<VT> sw{st.b0 + w * kWave, st.len + w * kWave, VALUES ? st.a + w * kWave : st.a};
+    for (int k = w; k < K; k += NWV)
+      part_products<false, VALUES, kWave, U, VT>(pr->part[k], i, active, lw, lS, sw, f);
+    group_sync<true>();
+    return;
   }
+  for (int k = 0; k < K; ++k)
+    part_products<BLOCK, VALUES, G, U, VT>(pr->part[k], i, active, l, lS, st, f);
 }
 
 // Adapter for per-product callbacks: f(col, val) for each valid product.

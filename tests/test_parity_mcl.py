@@ -116,32 +116,52 @@ def test_stepwise_random(B, n, d):
         Y, Xh = Yn, got
 
 
-def test_heavy_rows_and_topk_threshold(B):
-    """Rows with tens of thousands of products go through the bitmap kernel;
-    small topk exercises the threshold search there."""
-    n = 30000
-    X = synth.mcl_matrix(n, 6, 41, np.float32)
-    # make 3 columns of M dense-ish: rows of X with 4000 entries
-    rng = synth.rng_for(41, 2)
+def _heavy_input(n=30000, dense_rows=(7, 1234, 29999), width=4000, seed=41):
+    """X with a few rows of `width` entries: their products exceed every LDS
+    table, and more than 1024 entries per row exercise the entry cursors kept
+    outside registers."""
+    X = synth.mcl_matrix(n, 6, seed, np.float32)
+    rng = synth.rng_for(seed, 2)
     ip, ind, dat = [0], [], []
     for i in range(n):
         c, v = X.row(i)
-        if i in (7, 1234, 29999):
-            c = np.sort(rng.choice(n, 4000, replace=False)).astype(np.int32)
-            v = (1.0 - rng.random(4000))
+        if i in dense_rows:
+            c = np.sort(rng.choice(n, width, replace=False)).astype(np.int32)
+            v = (1.0 - rng.random(width))
             v = (v / v.sum()).astype(np.float32)
         ind.append(c); dat.append(v); ip.append(ip[-1] + len(c))
-    X = synth.HostCSR((n, n), np.array(ip, dtype=np.int64), np.concatenate(ind).astype(np.int32),
-                      np.concatenate(dat).astype(np.float32))
-    for topk, prune in [(1000, 1e-4), (50, 0.0), (3, 1e-6)]:
-        got = B.mcl_iteration(B.to_device(X), 2, prune, topk).to_host()
-        rows = np.array([7, 1234, 29999] + list(range(0, n, 97)))
-        _check_step(X, got, 2, prune, topk, rows)
+    return synth.HostCSR((n, n), np.array(ip, dtype=np.int64), np.concatenate(ind).astype(np.int32),
+                         np.concatenate(dat).astype(np.float32))
+
+
+@pytest.mark.parametrize("r,topk,prune", [(2, 1000, 1e-4), (2, 50, 0.0), (2, 3, 1e-6),
+                                          (3, 1000, 1e-4), (2, 1000, 1e-3)])
+def test_heavy_rows_and_topk_threshold(B, r, topk, prune):
+    """Rows with tens of thousands of products go through the column-panel
+    kernel (several panels, the last one partial); small topk exercises its
+    threshold search, prune 0 keeps every candidate, odd r disables the
+    candidate pre-filter, and a coarse prune empties rows."""
+    n = 30000
+    X = _heavy_input(n)
+    got = B.mcl_iteration(B.to_device(X), r, prune, topk).to_host()
+    rows = np.array([7, 1234, 29999] + list(range(0, n, 97)))
+    _check_step(X, got, r, prune, topk, rows)
+
+
+def test_heavy_rows_are_order_independent(B):
+    """Fixed-point accumulation: two runs give bit-identical heavy rows."""
+    X = _heavy_input(20000, dense_rows=(0, 5, 19999), width=3000, seed=44)
+    a = B.mcl_iteration(B.to_device(X), 2, 1e-5, 1000).to_host()
+    b = B.mcl_iteration(B.to_device(X), 2, 1e-5, 1000).to_host()
+    assert np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+    for i in (0, 5, 19999):
+        s, e = a.indptr[i], a.indptr[i + 1]
+        assert np.array_equal(a.data[s:e], b.data[s:e])
 
 
 def test_handover_path_forced(B):
-    """A one-slot probe window sends most rows to the bitmap kernel: same
-    results."""
+    """A one-slot probe window sends most rows to the column-panel kernel:
+    same results."""
     X = synth.mcl_matrix(4000, 10, 43, np.float32)
     t = B.default_tuning()
     t.max_window = 1
