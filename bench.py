@@ -14,8 +14,9 @@ inputs resident in HBM.  Prints one JSON line.
 
 Also reported (unless --only-plain): the batched stage sequence (8 uneven
 block products summed into one C; per-block eager launches + sparse sum vs
-the fused product captured as one graph) and the backward pass at fixed
-sparsity; with --mcl, 10 Markov-clustering iterations in one graph.
+the fused product captured as one graph), uniform and R-MAT variants, and
+the backward pass at fixed sparsity; with --mcl, 10 Markov-clustering
+iterations in one graph.
 """
 from __future__ import annotations
 
@@ -113,23 +114,12 @@ def _events(n):
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
 
 
-def bench_batched(args):
-    """8 uneven block products summed into one C: per-block eager launches
-    (symbolic with read-back + numeric per block, then the sparse sum) vs the
-    fused product captured as one graph."""
+def _time_batched(args, pairs, m, bytes_in):
+    """Per-block eager launches (symbolic with read-back + numeric per block,
+    then the sparse sum) against the fused product captured as one graph."""
     import torch
-    from paper_2603_21444_amd import binding, synth
+    from paper_2603_21444_amd import binding
     from paper_2603_21444_amd.graph import StageGraph
-    m, n, K = 1 << 18, 1 << 20, 8
-    rng = synth.rng_for(SEED + 3, 11)
-    kdims = rng.integers(1 << 18, (1 << 20) + 1, size=K)
-    pairs = []
-    for k in range(K):
-        Ak = synth.varnnz_csr(m, int(kdims[k]), 4, 32, SEED + 3, np.float32, "normal", stream=2 * k)
-        Bk = synth.varnnz_csr(int(kdims[k]), n, 4, 32, SEED + 3, np.float32, "normal", stream=2 * k + 1)
-        pairs.append((binding.to_device(Ak), binding.to_device(Bk)))
-        log(f"[bench] batched block {k}: K_k={int(kdims[k])}")
-    bytes_in = sum(csr_bytes(a.shape[0], a.nnz, 4) + csr_bytes(b.shape[0], b.nnz, 4) for a, b in pairs)
 
     def eager():
         parts = [binding.spgemm(a, b) for a, b in pairs]
@@ -157,15 +147,13 @@ def bench_batched(args):
     graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     Cg = g.result()
     assert Cg.nnz == nnz, (Cg.nnz, nnz)
-    _, products = g.plan.info()
-    if products < 0:
-        plan = binding.Plan()
-        plan.symbolic([a for a, _ in pairs], [b for _, b in pairs])
-        _, products = plan.info()
+    plan = binding.Plan()
+    plan.symbolic([a for a, _ in pairs], [b for _, b in pairs])
+    _, products = plan.info()
+    del g, Cg
+    torch.cuda.empty_cache()
     alg = bytes_in + 4 * (m + 1) + 8 * nnz
     return {
-        "workload": "C = sum_k A_k B_k, 8 blocks, m = 2^18, n = 2^20, inner K_k ~ U[2^18, 2^20], "
-                    "4..32 nnz/row, FP32 N(0,1)",
         "products": int(products), "nnz_C": int(nnz),
         "graph_ms": round(graph_ms, 3), "eager_per_block_ms": round(eager_ms, 3),
         "graph_gflops": round(2 * products / graph_ms / 1e6, 2),
@@ -173,6 +161,43 @@ def bench_batched(args):
         "graph_speedup": round(eager_ms / graph_ms, 3),
         "graph_alg_GBs": round(alg / graph_ms / 1e6, 1),
     }
+
+
+def bench_batched(args):
+    """8 uneven block products summed into one C (uniform variant)."""
+    from paper_2603_21444_amd import binding, synth
+    m, n, K = 1 << 18, 1 << 20, 8
+    rng = synth.rng_for(SEED + 3, 11)
+    kdims = rng.integers(1 << 18, (1 << 20) + 1, size=K)
+    pairs = []
+    for k in range(K):
+        Ak = synth.varnnz_csr(m, int(kdims[k]), 4, 32, SEED + 3, np.float32, "normal", stream=2 * k)
+        Bk = synth.varnnz_csr(int(kdims[k]), n, 4, 32, SEED + 3, np.float32, "normal", stream=2 * k + 1)
+        pairs.append((binding.to_device(Ak), binding.to_device(Bk)))
+    log("[bench] batched blocks generated")
+    bytes_in = sum(csr_bytes(a.shape[0], a.nnz, 4) + csr_bytes(b.shape[0], b.nnz, 4) for a, b in pairs)
+    r = _time_batched(args, pairs, m, bytes_in)
+    r["workload"] = ("C = sum_k A_k B_k, 8 blocks, m = 2^18, n = 2^20, inner K_k ~ U[2^18, 2^20], "
+                     "4..32 nnz/row, FP32 N(0,1)")
+    return r
+
+
+def bench_batched_rmat(args):
+    """Power-law variant: A = R-MAT scale 20, edge factor 16, split into 8
+    uneven inner blocks; B 2^20 x 2^20 with 4..32 uniform columns per row."""
+    from paper_2603_21444_amd import binding, synth
+    n = 1 << 20
+    seed = SEED + 6
+    A = synth.rmat_csr(20, 16, seed=seed, dtype=np.float32, values="normal", stream=0)
+    Bm = synth.varnnz_csr(n, n, 4, 32, seed, np.float32, "normal", stream=1)
+    bounds = synth.column_blocks(n, 8, n // 16, n // 4, seed)
+    pairs = [(binding.to_device(a), binding.to_device(b)) for a, b in synth.split_inner(A, Bm, bounds)]
+    log("[bench] R-MAT blocks generated")
+    bytes_in = sum(csr_bytes(a.shape[0], a.nnz, 4) + csr_bytes(b.shape[0], b.nnz, 4) for a, b in pairs)
+    r = _time_batched(args, pairs, n, bytes_in)
+    r["workload"] = ("C = sum_k A_k B_k, A = R-MAT(0.57,0.19,0.19,0.05) scale 20 edge factor 16 split "
+                     "into 8 uneven inner blocks, B 2^20 x 2^20 with 4..32 nnz/row, FP32 N(0,1)")
+    return r
 
 
 def bench_backward(args):
@@ -322,6 +347,9 @@ def main():
     if not args.only_plain:
         log("[bench] batched stage sequence")
         out["batched_graph"] = bench_batched(args)
+        torch.cuda.empty_cache()
+        log("[bench] batched stage sequence, R-MAT")
+        out["batched_graph_rmat"] = bench_batched_rmat(args)
         torch.cuda.empty_cache()
         log("[bench] backward")
         out["backward"] = bench_backward(args)

@@ -88,12 +88,13 @@ __device__ inline int mbcnt(uint64_t mask) {
 
 // Order-preserving home slot: floor(col * T / n) computed as the high half of
 // col * floor(T * 2^32 / n); `mul` == 0 means T >= n and the slot is col.
-__device__ inline uint32_t mono_slot(uint32_t col, uint32_t mul) {
-  return mul ? __umulhi(col, mul) : col;
-}
+__device__ inline uint32_t mono_slot(uint32_t col, uint32_t mul) { return __umulhi(col, mul); }
 
+// Multiplier of the order-preserving home slot floor(col * T / n).  With
+// T >= n it is 2^32 - 1, giving max(col - 1, 0): still non-decreasing in col
+// and below T, and the slot computation needs no branch.
 __host__ inline uint32_t mono_mul(int64_t T, int64_t n) {
-  if (T >= n) return 0u;
+  if (T >= n) return 0xffffffffu;
   return (uint32_t)(((uint64_t)T << 32) / (uint64_t)n);
 }
 

@@ -29,11 +29,11 @@ struct WsLayout {
   size_t mcl_rabs = 0, mcl_slots = 0;  // MCL only: row sums of |x|, heavy-row slots
 };
 
-// MCL heavy rows: per-slot scratch (candidate list + entry cursors, 16 B per
-// column) and the number of slots (concurrent heavy rows, at most 512, at
-// most 4 GiB of scratch).
+// MCL heavy rows: per-slot scratch (candidate list, and cursor, end and value
+// of the entries of rows too long for LDS: 20 B per column) and the number of
+// slots (concurrent heavy rows, at most 512, at most 4 GiB of scratch).
 inline size_t mcl_slot_bytes(int64_t n) {
-  return ((size_t)16 * (size_t)(n > 0 ? n : 1) + 255) & ~(size_t)255;
+  return ((size_t)20 * (size_t)(n > 0 ? n : 1) + 255) & ~(size_t)255;
 }
 inline int mcl_heavy_slots(int64_t n) {
   const int64_t s = ((int64_t)4 << 30) / (int64_t)mcl_slot_bytes(n);

@@ -271,11 +271,14 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
 // Heavy rows: column panels with fixed-point accumulators in LDS.
 //
 // A heavy row (more products than an LDS table holds, or handed over by the
-// LDS kernel) is swept in panels of kPanel consecutive columns.  Each of the
-// block's 1024 threads owns one entry a_ik of X row i and walks B row k
-// (sorted, as X is canonical) with a cursor held in registers, kPB elements
-// per load round; the round that ends a panel already holds the first
-// elements of the next one.  A product a_ik * b_kj (exact in FP64) is scaled
+// LDS kernel) is swept in panels of kPanel consecutive columns.  Every entry
+// a_ik of X row i keeps a cursor into B row k (sorted, as X is canonical).
+// In a panel, S lanes of a wave read S consecutive elements of one entry's B
+// row (coalesced), a wave serves kPU entries at once so that several loads
+// are in flight, and a ballot over the S lanes tells how far the entry got
+// (elements are ascending, so those inside the panel are a prefix).  S is
+// chosen per row from the mean number of elements an entry has per panel.
+// A product a_ik * b_kj (exact in FP64) is scaled
 // by 2^s and rounded to an int64 that is added into the panel's LDS slot with
 // an integer atomic: integer LDS atomics are far cheaper than float ones on
 // this chip, and the sum no longer depends on the order of the adds.  The
@@ -291,10 +294,12 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
 // test on p / sum, the top-k threshold is found by bisection on the float
 // bit patterns, ties go to the smaller columns (list order), and the result is
 // renormalised and written in column order.
-constexpr int kPanel = 8192;  // columns per panel: 64 KiB of int64 in LDS
-constexpr int kPT = 1024;     // threads of a heavy block
-constexpr int kPB = 8;        // B elements per entry per load round
-static_assert(kPanel == kPT * 8, "the epilogue gives each thread 8 columns");
+constexpr int kPanel = 16384;  // columns per panel: 128 KiB of int64 in LDS
+constexpr int kPT = 1024;      // threads of a heavy block
+constexpr int kCPT = kPanel / kPT;  // panel columns per thread in the epilogue
+constexpr int kPU = 4;        // entry groups a wave serves at once
+constexpr int kPE = 1024;     // entries whose cursors stay in LDS
+static_assert(kCPT == 16, "the epilogue reads one 16-bit half of a bitmap word per thread");
 
 struct PanelRed {
   double s;
@@ -352,44 +357,73 @@ __device__ __forceinline__ PanelRed panel_reduce(double s, int c, int mn, unsign
   return PanelRed{ts, tt, tp + x - c, tm, tb};
 }
 
-template <int NB>
-__device__ __forceinline__ void load_round(const SPG_GLOBAL int32_t *bcol,
-                                           const SPG_GLOBAL float *bval, int cur, int end,
-                                           int (&bc)[NB], float (&bv)[NB]) {
-#pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    const bool in = cur + u < end;
-    bc[u] = in ? bcol[cur + u] : INT32_MAX;
-    bv[u] = in ? bval[cur + u] : 0.f;
-  }
-}
-
-// Adds the products of one entry that fall in [plo, plo + kPanel); on return
-// bc/bv hold the entry's elements from the new cursor on.
-template <int NB>
-__device__ __forceinline__ void panel_entry(const SPG_GLOBAL int32_t *bcol,
-                                            const SPG_GLOBAL float *bval, int &cur, int end,
-                                            double a, double sigma, int plo, uint32_t width,
-                                            unsigned long long *pacc, uint32_t *pbm,
-                                            int (&bc)[NB], float (&bv)[NB]) {
+// Adds the products of entries [0, nA) that fall in [plo, plo + width) and
+// advances their cursors; returns this lane's smallest next column.
+template <typename CurT>
+__device__ __forceinline__ int panel_accumulate(const SPG_GLOBAL int32_t *bcol,
+                                                const SPG_GLOBAL float *bval, CurT *ecur,
+                                                const CurT *eend, const float *eval, int nA,
+                                                int lS, double sigma, int plo, uint32_t width,
+                                                unsigned long long *pacc, uint32_t *pbm) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int S = 1 << lS, EPW = kWave >> lS;
+  const int sub = lane >> lS, q = lane & (S - 1), base = sub << lS;
   const int phi = plo + kPanel;
-  while (bc[0] < phi) {
-    int k = 0;
+  int tmn = INT32_MAX;
+  for (int e0 = w * EPW * kPU; e0 < nA; e0 += (kPT / kWave) * EPW * kPU) {
+    int c[kPU], en[kPU];
+    float a[kPU];
+    bool act[kPU];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      if (k == u && bc[u] < phi) {
-        k = u + 1;
-        const uint32_t cl = (uint32_t)(bc[u] - plo);
-        if (cl < width) {  // columns outside [0, n) are skipped
-          const long long q = __double2ll_rn(a * (double)bv[u] * sigma);
-          atomicAdd(&pacc[cl], (unsigned long long)q);
+    for (int u = 0; u < kPU; ++u) {
+      const int e = e0 + u * EPW + sub;
+      act[u] = e < nA;
+      c[u] = act[u] ? (int)ecur[e] : 0;
+      en[u] = act[u] ? (int)eend[e] : 0;
+      a[u] = act[u] ? eval[e] : 0.f;
+    }
+    bool more = true;
+    while (more) {
+      int col[kPU];
+      float v[kPU];
+#pragma unroll
+      for (int u = 0; u < kPU; ++u) {
+        const int idx = c[u] + q;
+        const bool ld = act[u] && idx < en[u];
+        col[u] = ld ? bcol[idx] : INT32_MAX;
+        v[u] = ld ? bval[idx] : 0.f;
+      }
+      more = false;
+#pragma unroll
+      for (int u = 0; u < kPU; ++u) {
+        const bool in = col[u] < phi;
+        const uint32_t cl = (uint32_t)(col[u] - plo);
+        if (in && cl < width) {  // columns outside [0, n) are skipped
+          const long long qv = __double2ll_rn((double)a[u] * (double)v[u] * sigma);
+          atomicAdd(&pacc[cl], (unsigned long long)qv);
           atomicOr(&pbm[cl >> 5], 1u << (cl & 31));
         }
+        const uint64_t m = __ballot(in);
+        const int k = __popcll((m >> base) & (S == kWave ? ~0ull : ((1ull << S) - 1)));
+        const int nxt = __shfl(col[u], base + (k < S ? k : 0));
+        if (act[u]) {
+          c[u] += k;
+          if (k < S) {  // the entry left the panel (or its row ended)
+            act[u] = false;
+            tmn = min(tmn, nxt);
+          }
+        }
+        more = more || act[u];
       }
+      more = __any(more);
     }
-    cur += k;
-    load_round(bcol, bval, cur, end, bc, bv);
+#pragma unroll
+    for (int u = 0; u < kPU; ++u) {
+      const int e = e0 + u * EPW + sub;
+      if (e < nA && q == 0) ecur[e] = (CurT)c[u];
+    }
   }
+  return tmn;
 }
 
 __global__ __launch_bounds__(kPT) void k_mcl_panel(
@@ -402,6 +436,8 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
   __shared__ double rs[kPT / kWave];
   __shared__ int rc[kPT / kWave], rm[kPT / kWave];
   __shared__ unsigned long long rb[kPT / kWave];
+  __shared__ int s_cur[kPE], s_end[kPE];
+  __shared__ float s_val[kPE];
   const int n = pr->n;
   const int tid = threadIdx.x;
   char *sp = scratch + (size_t)blockIdx.x * slot_bytes;
@@ -409,6 +445,7 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
   float *lval = reinterpret_cast<float *>(sp + (size_t)4 * n);
   int32_t *ecur = reinterpret_cast<int32_t *>(sp + (size_t)8 * n);
   int32_t *eend = reinterpret_cast<int32_t *>(sp + (size_t)12 * n);
+  float *evalg = reinterpret_cast<float *>(sp + (size_t)16 * n);
   __shared__ int stat0;
   if (tid == 0) stat0 = hdr->status;
   __syncthreads();
@@ -432,30 +469,26 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
       if (tid == 0) atomicOr(&hdr->status, kStatInvalid);
       break;
     }
-    // entries: the first kPT in registers, the rest in the slot scratch
-    int cur = 0, end = 0;
-    double a0 = 0.0, sb = 0.0;
-    int mn = INT32_MAX;
+    // entries: cursor, end and value, in LDS for rows of at most kPE
+    // entries, else in the slot scratch
+    const bool lds_state = nA <= kPE;
+    int *ccur = lds_state ? s_cur : ecur;
+    int *cend = lds_state ? s_end : eend;
+    float *cval = lds_state ? s_val : evalg;
+    double sb = 0.0;
+    int mn = INT32_MAX, plen = 0;
     for (int e = tid; e < nA; e += kPT) {
       const int k = gp(P.acol)[as + e];
       const float av = gp(static_cast<const float *>(P.aval))[as + e];
       const int b0 = gp(P.brp)[k], b1 = gp(P.brp)[k + 1];
       sb += fabs((double)av) * rabs[k];
-      if (e == tid) {
-        cur = b0;
-        end = b1;
-        a0 = av;
-      } else {
-        ecur[e] = b0;
-        eend[e] = b1;
-        if (b0 < b1) mn = min(mn, bcol[b0]);
-      }
+      ccur[e] = b0;
+      cend[e] = b1;
+      cval[e] = av;
+      plen += b1 - b0;
+      if (b0 < b1) mn = min(mn, bcol[b0]);
     }
-    int bc[kPB];
-    float bv[kPB];
-    load_round(bcol, bval, cur, end, bc, bv);
-    mn = min(mn, bc[0]);
-    PanelRed R = panel_reduce(sb, 0, mn, 0ull, rs, rc, rm, rb);
+    PanelRed R = panel_reduce(sb, plen, mn, 0ull, rs, rc, rm, rb);
     __syncthreads();
     // scale 2^s with 2^(62-s) > the row's bound on sum |a b|
     double sigma = 1.0;
@@ -468,6 +501,14 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
         sigma = ldexp(1.0, 62 - ex);
       }
     }
+    const double inv_sigma = 1.0 / sigma;  // exact: sigma is a power of two
+    // lanes per entry: about the mean number of an entry's elements per panel
+    int lS = 2;
+    {
+      const double per = (double)R.total / (double)(nA > 0 ? nA : 1) /
+                         (double)((n + kPanel - 1) / kPanel);
+      while (lS < 6 && (double)(1 << lS) < per) ++lS;
+    }
     int mnext = R.mn;
     double scum = 0.0;
     int nc = 0;
@@ -475,28 +516,17 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
     while (mnext < n) {
       const int plo = mnext & ~(kPanel - 1);
       const uint32_t width = plo < 0 ? 0u : (uint32_t)min(kPanel, n - plo);
-      panel_entry(bcol, bval, cur, end, a0, sigma, plo, width, pacc, pbm, bc, bv);
-      int tmn = bc[0];
-      for (int e = tid + kPT; e < nA; e += kPT) {
-        int c2 = ecur[e];
-        const int e2 = eend[e];
-        int bc2[2];
-        float bv2[2];
-        load_round(bcol, bval, c2, e2, bc2, bv2);
-        panel_entry(bcol, bval, c2, e2, (double)gp(static_cast<const float *>(P.aval))[as + e],
-                    sigma, plo, width, pacc, pbm, bc2, bv2);
-        ecur[e] = c2;
-        tmn = min(tmn, bc2[0]);
-      }
+      const int tmn = panel_accumulate(bcol, bval, ccur, cend, cval, nA, lS, sigma, plo, width,
+                                       pacc, pbm);
       __syncthreads();
-      // epilogue of the panel: thread tid owns columns plo + 8 tid .. + 7
+      // epilogue of the panel: thread tid owns columns plo + 16 tid .. + 15
       const double thr = even ? (double)prune * scum * (1.0 - 1.0 / 1024.0) : -HUGE_VAL;
-      const uint32_t bits = (pbm[tid >> 2] >> ((tid & 3) * 8)) & 0xffu;
+      const uint32_t bits = (pbm[tid >> 1] >> ((tid & 1) * 16)) & 0xffffu;
       double ps = 0.0;
       int cnt = 0;
       for (uint32_t b = bits; b; b &= b - 1) {
-        const int cl = tid * 8 + __ffs(b) - 1;
-        const float pw = ipow((float)((double)(long long)pacc[cl] / sigma), r);
+        const int cl = tid * kCPT + __ffs(b) - 1;
+        const float pw = ipow((float)((double)(long long)pacc[cl] * inv_sigma), r);
         ps += (double)pw;
         const unsigned long long key = vc_key(pw, plo + cl);
         best = key > best ? key : best;
@@ -505,8 +535,8 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
       R = panel_reduce(ps, cnt, tmn, 0ull, rs, rc, rm, rb);
       int o = nc + R.excl;
       for (uint32_t b = bits; b; b &= b - 1) {
-        const int cl = tid * 8 + __ffs(b) - 1;
-        const float pw = ipow((float)((double)(long long)pacc[cl] / sigma), r);
+        const int cl = tid * kCPT + __ffs(b) - 1;
+        const float pw = ipow((float)((double)(long long)pacc[cl] * inv_sigma), r);
         pacc[cl] = 0ull;
         if ((double)pw >= thr) {
           lcol[o] = plo + cl;
@@ -514,7 +544,7 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
           ++o;
         }
       }
-      if ((tid & 3) == 0) pbm[tid >> 2] = 0u;
+      if ((tid & 1) == 0) pbm[tid >> 1] = 0u;
       scum += R.s;
       nc += R.total;
       mnext = R.mn;

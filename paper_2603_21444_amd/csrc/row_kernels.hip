@@ -198,8 +198,27 @@ struct NumInsert {
   }
 };
 
+// FP32 inserts (slot table, see slot_insert).
+template <bool PACK>
+struct NumInsertF {
+  unsigned long long *slot;
+  int *adj;
+  int *flag;
+  uint32_t mul;
+  int maxwin;
+  template <int N>
+  __device__ __forceinline__ void batch(const int (&col)[N], const float (&v)[N]) {
+    slot_insert<PACK, N>(slot, adj, flag, mul, maxwin, col, v);
+  }
+};
+
+// Waves per SIMD the numeric kernel is compiled for (bounds its registers):
+// block groups hold larger tables, which leave room for fewer blocks per CU.
+template <int G>
+constexpr int num_waves() { return G >= 512 ? 4 : (G >= 128 ? 6 : SPG_NUM_WAVES); }
+
 template <int G, typename VT, bool PACK>
-__global__ __launch_bounds__(Geom<G>::WG, SPG_NUM_WAVES) void k_num_rows(const Problem *__restrict__ pr,
+__global__ __launch_bounds__(Geom<G>::WG, num_waves<G>()) void k_num_rows(const Problem *__restrict__ pr,
                                                           const int32_t *__restrict__ rows,
                                                           WsHeader *__restrict__ hdr, int bin,
                                                           int lS, int TT, uint32_t mul,
@@ -210,16 +229,22 @@ __global__ __launch_bounds__(Geom<G>::WG, SPG_NUM_WAVES) void k_num_rows(const P
                                                           int32_t *__restrict__ fb_rows) {
   using GM = Geom<G>;
   using KC = KeyCode<PACK>;
+  constexpr bool F32 = sizeof(VT) == 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int rslot = threadIdx.x / G, l = threadIdx.x % G;
+  // F32: slots u64[R*TT] | sa | adj | sb | sl | rowflag | wtot
+  // F64: vals VT[R*TT] | sa | keys int[R*TT] | adj | sb | sl | rowflag | wtot
+  unsigned long long *slots_all = reinterpret_cast<unsigned long long *>(smem_raw);
   VT *vals_all = reinterpret_cast<VT *>(smem_raw);
-  VT *sa_all = vals_all + (size_t)GM::R * TT;
+  VT *sa_all = F32 ? reinterpret_cast<VT *>(slots_all + (size_t)GM::R * TT)
+                   : vals_all + (size_t)GM::R * TT;
   int *keys_all = reinterpret_cast<int *>(sa_all + (size_t)GM::R * G);
-  int *adj_all = keys_all + (size_t)GM::R * TT;
+  int *adj_all = F32 ? keys_all : keys_all + (size_t)GM::R * TT;
   int *sb_all = adj_all + (PACK ? 0 : (size_t)GM::R * TT);
   int *sl_all = sb_all + (size_t)GM::R * G;
   int *rowflag = sl_all + (size_t)GM::R * G;
   int *wtot = rowflag + GM::R;
+  unsigned long long *slot = slots_all + (size_t)rslot * TT;
   VT *val = vals_all + (size_t)rslot * TT;
   int *key = keys_all + (size_t)rslot * TT;
   int *adj = adj_all + (size_t)rslot * TT;
@@ -227,71 +252,96 @@ __global__ __launch_bounds__(Geom<G>::WG, SPG_NUM_WAVES) void k_num_rows(const P
   if (hdr->status) return;
   const int count = hdr->bin_count[bin];
   const int start = hdr->bin_start[bin];
-  const int c = TT / G;  // slots per lane in the output pass of block groups (odd)
+  auto key_at = [&](int s) { return F32 ? slot_key(slot[s]) : key[s]; };
   for (int ri = blockIdx.x * GM::R + rslot; ri < count; ri += gridDim.x * GM::R) {
     const int i = uniform_if_wave<G>(rows[start + ri]);
-    {
+    if (F32) {
+      int4 *s4 = reinterpret_cast<int4 *>(slot);
+      for (int s = l; s < TT / 2; s += G) s4[s] = make_int4(kEmpty, 0, kEmpty, 0);
+    } else {
       int4 *k4 = reinterpret_cast<int4 *>(key);
       for (int s = l; s < TT / 4; s += G) k4[s] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
-      if (!PACK) {
-        int4 *a4 = reinterpret_cast<int4 *>(adj);
-        for (int s = l; s < TT / 4; s += G) a4[s] = make_int4(0, 0, 0, 0);
-      }
       if (GM::BLOCK)
         for (int s = l; s < TT; s += G) val[s] = VT(0);
     }
+    if (!PACK) {
+      int4 *a4 = reinterpret_cast<int4 *>(adj);
+      for (int s = l; s < TT / 4; s += G) a4[s] = make_int4(0, 0, 0, 0);
+    }
     if (l == 0) rowflag[rslot] = 0;
     group_sync<GM::BLOCK>();
-    NumInsert<VT, PACK, !GM::BLOCK> ins{key, val, adj, rowflag + rslot, mul, maxwin};
-    for_each_product<GM::BLOCK, true, G, kUnroll, VT>(pr, i, true, l, lS, st, ins);
+    if constexpr (F32) {
+      NumInsertF<PACK> ins{slot, adj, rowflag + rslot, mul, maxwin};
+      for_each_product<GM::BLOCK, true, G, kUnroll, VT>(pr, i, true, l, lS, st, ins);
+    } else {
+      NumInsert<VT, PACK, !GM::BLOCK> ins{key, val, adj, rowflag + rslot, mul, maxwin};
+      for_each_product<GM::BLOCK, true, G, kUnroll, VT>(pr, i, true, l, lS, st, ins);
+    }
     group_sync<GM::BLOCK>();
     const bool ok = rowflag[rslot] == 0;
     const int rs = crp[i];
     const int nnz = crp[i + 1] - rs;
-    int total;
     SPG_GLOBAL int32_t *cb = gpw(ccol) + rs;
     SPG_GLOBAL VT *vb = gpw(cval) + rs;
-    if (!GM::BLOCK) {
-      // slots s0 + l of each round: one ballot gives every lane its rank
-      const int g0 = (lane_id() / G) * G;
-      const uint64_t gm = (G >= kWave) ? ~0ull : (((1ull << G) - 1ull) << g0);
-      const uint64_t below = lanes_below();
-      int base = 0;
-      for (int s0 = 0; s0 < TT; s0 += G) {
-        const int s = s0 + l;
-        const int w = key[s];
-        const uint64_t m = __ballot(w != kEmpty) & gm;
-        if (ok && w != kEmpty && nnz > 0) {
-          int rr = base + __popcll(m & below) + (PACK ? KC::adj(w) : adj[s]);
-          rr = rr < 0 ? 0 : (rr >= nnz ? nnz - 1 : rr);  // in bounds even for a changed pattern
-          cb[(uint32_t)rr] = KC::col(w);
-          vb[(uint32_t)rr] = val[s];
-        }
-        base += __popcll(m);
+    // Output: rounds of 64 (or G) consecutive slots; one ballot gives every
+    // lane the rank of its key among the round's, so the writes of a round
+    // are contiguous.  Block groups first count each wave's slot range and
+    // scan the counts across the waves.
+    const int gsz = GM::BLOCK ? kWave : G;
+    const int g0 = (lane_id() / gsz) * gsz;
+    const uint64_t gm = (gsz >= kWave) ? ~0ull : (((1ull << gsz) - 1ull) << g0);
+    const uint64_t below = lanes_below();
+    const int wl = GM::BLOCK ? l % kWave : l;
+    int lo = 0, hi = TT, base = 0, total = 0;
+    if (GM::BLOCK) {
+      constexpr int NW = GM::BLOCK ? G / kWave : 1;
+      const int w = l / kWave;
+      const int per = ((TT + kWave - 1) / kWave + NW - 1) / NW * kWave;
+      lo = min(TT, w * per);
+      hi = min(TT, lo + per);
+      int cw = 0;
+      for (int s0 = lo; s0 < hi; s0 += kWave) {
+        const int s = s0 + wl;
+        cw += __popcll(__ballot(s < hi && key_at(s) != kEmpty));
       }
-      total = base;
-    } else {
-      const int s0 = l * c;
-      int mine = 0;
-      for (int j = 0; j < c; ++j) mine += key[s0 + j] != kEmpty;
-      int r = group_excl_scan<GM::BLOCK, G>(mine, l, wtot, total);
-      if (ok && nnz > 0) {
-        for (int j = 0; j < c; ++j) {
-          const int w = key[s0 + j];
-          if (w != kEmpty) {
-            int rr = r + (PACK ? KC::adj(w) : adj[s0 + j]);
-            rr = rr < 0 ? 0 : (rr >= nnz ? nnz - 1 : rr);
-            cb[(uint32_t)rr] = KC::col(w);
-            vb[(uint32_t)rr] = val[s0 + j];
-            ++r;
-          }
-        }
+      if (wl == 0) wtot[w] = cw;
+      __syncthreads();
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) {
+        const int c = wtot[ww];
+        base += ww < w ? c : 0;
+        total += c;
       }
+      __syncthreads();
     }
+    for (int s0 = lo; s0 < hi; s0 += gsz) {
+      const int s = s0 + wl;
+      int w = kEmpty;
+      VT v = VT(0);
+      if (s < hi) {
+        if constexpr (F32) {
+          const unsigned long long sv = slot[s];
+          w = slot_key(sv);
+          v = slot_val(sv);
+        } else {
+          w = key[s];
+          v = val[s];
+        }
+      }
+      const uint64_t m = __ballot(w != kEmpty) & gm;
+      if (ok && w != kEmpty && nnz > 0) {
+        int rr = base + __popcll(m & below) + (PACK ? KC::adj(w) : adj[s]);
+        rr = rr < 0 ? 0 : (rr >= nnz ? nnz - 1 : rr);  // in bounds even for a changed pattern
+        cb[(uint32_t)rr] = KC::col(w);
+        vb[(uint32_t)rr] = v;
+      }
+      base += __popcll(m);
+    }
+    if (!GM::BLOCK) total = base;
     if (ok && l == 0 && total != nnz) atomicOr(&hdr->status, kStatInvalid);
     if (l == 0 && !ok) {
-      const int slot = atomicAdd(&hdr->fallback_count, 1);
-      fb_rows[slot] = i;
+      const int slot_i = atomicAdd(&hdr->fallback_count, 1);
+      fb_rows[slot_i] = i;
     }
     group_sync<GM::BLOCK>();
   }
@@ -561,9 +611,13 @@ int num_table_slots(int b, int G) {
   return c * G;
 }
 
+// Table slots of the numeric kernel: T plus the probe tail, a multiple of 64
+// (its output reads rounds of 64 slots; block groups split them by wave).
+int num_rows_slots(int b) { return (bin_slots(b) + kTail + kWave - 1) / kWave * kWave; }
+
 size_t num_lds_bytes(int b, int G, size_t vbytes, bool pack) {
   const int WG = wg_for(G), R = WG / G;
-  const size_t TT = (size_t)num_table_slots(b, G);
+  const size_t TT = (size_t)num_rows_slots(b);
   return (size_t)R * TT * (vbytes + (pack ? 4 : 8)) + (size_t)R * G * (vbytes + 8) +
          (size_t)R * 4 + 64;
 }
@@ -672,7 +726,7 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
     const int WG = wg_for(G);
     const int R = WG / G;
     const int T = bin_slots(b);
-    const int TT = num_table_slots(b, G);
+    const int TT = num_rows_slots(b);
     const size_t lds = num_lds_bytes(b, G, sizeof(VT), pack);
     const int grid = grid_for(bins_count(bp, b, b), R, D.cus * blocks_per_cu(lds, WG, D.lds_per_cu));
     const uint32_t mul = mono_mul(T, bp.n);

@@ -114,6 +114,89 @@ struct KeyCode {
   __device__ static int adj(int w) { return PACK ? (int)((uint32_t)w >> 24) - 128 : 0; }
 };
 
+// FP32 numeric tables keep a key word and its value in one 64-bit slot (key
+// in the low half, value bits in the high half).  A column's first insert
+// writes both with one 64-bit compare-and-swap, so no lane can see the key
+// before the value; a repeat adds its value with a compare-and-swap loop on
+// the slot.  LDS float atomics are slow on this chip, and repeats are rare
+// for most rows, so nearly every product costs one LDS atomic and no fence.
+// The rank counters of PACK keys are updated with 64-bit adds on the slot:
+// the counter byte stays within [128 - 2*kTail, 128 + 2*kTail], so no carry
+// or borrow reaches the value half.
+constexpr unsigned long long kEmptySlot = 0xffffffffull;  // key kEmpty, value 0
+
+__device__ __forceinline__ unsigned long long slot_make(int kw, float v) {
+  return ((unsigned long long)__float_as_uint(v) << 32) | (uint32_t)kw;
+}
+__device__ __forceinline__ int slot_key(unsigned long long s) { return (int)(uint32_t)s; }
+__device__ __forceinline__ float slot_val(unsigned long long s) {
+  return __uint_as_float((uint32_t)(s >> 32));
+}
+
+// Inserts N products per lane (col < 0: none) into an order-preserving FP32
+// slot table with forward probing of at most maxwin slots (*flag = 1 when a
+// probe is longer: the row is redone elsewhere), then lets every displaced
+// first insert count the larger keys on its probe path (rank counters).  The
+// first probes of all N products are issued before any result is examined.
+template <bool PACK, int N>
+__device__ __forceinline__ void slot_insert(unsigned long long *slot, int *adj, int *flag,
+                                            uint32_t mul, int maxwin, const int (&col)[N],
+                                            const float (&v)[N]) {
+  using KC = KeyCode<PACK>;
+  int h[N], d[N];
+  unsigned long long old[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    h[u] = (int)mono_slot((uint32_t)col[u], mul);
+    old[u] = col[u] >= 0 ? atomicCAS(&slot[h[u]], kEmptySlot, slot_make(KC::make(col[u]), v[u]))
+                         : kEmptySlot;
+  }
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    d[u] = 0;
+    if (col[u] < 0) continue;
+    while (old[u] != kEmptySlot) {
+      if (KC::col(slot_key(old[u])) == col[u]) {  // repeat: add into the slot
+        unsigned long long cur = old[u];
+        while (true) {
+          const unsigned long long nw =
+              (cur & 0xffffffffull) |
+              ((unsigned long long)__float_as_uint(slot_val(cur) + v[u]) << 32);
+          const unsigned long long got = atomicCAS(&slot[h[u]], cur, nw);
+          if (got == cur) break;
+          cur = got;
+        }
+        d[u] = -1;
+        break;
+      }
+      if (d[u] == maxwin) {  // long probe: the row is redone elsewhere
+        *flag = 1;
+        d[u] = -1;
+        break;
+      }
+      ++d[u];
+      ++h[u];  // h <= home + maxwin < table size
+      old[u] = atomicCAS(&slot[h[u]], kEmptySlot, slot_make(KC::make(col[u]), v[u]));
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    if (col[u] < 0 || d[u] <= 0) continue;  // displaced first inserts only
+    int larger = 0;
+    for (int t = h[u] - d[u]; t < h[u]; ++t) {
+      if (KC::col(slot_key(slot[t])) > col[u]) {
+        if (PACK) atomicAdd(&slot[t], 1ull << 24);
+        else atomicAdd(&adj[t], 1);
+        ++larger;
+      }
+    }
+    if (larger) {
+      if (PACK) atomicAdd(&slot[h[u]], 0ull - ((unsigned long long)larger << 24));
+      else atomicSub(&adj[h[u]], larger);
+    }
+  }
+}
+
 // Staging area of one group in LDS: one A entry per lane of a chunk.
 template <typename VT>
 struct Stage {

@@ -66,6 +66,54 @@ def test_batched_sum_of_uneven_blocks(B, dtype):
     assert np.array_equal(ref.indices, full.indices)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_rmat_product_and_batched(B, dtype):
+    """Power-law rows (R-MAT (0.57, 0.19, 0.19, 0.05), scale 15, edge factor
+    16): empty rows, every LDS bin and hub rows beyond the LDS tables.  The
+    plain product and the sum of its 8 uneven inner blocks in one pass both
+    match the oracle."""
+    n = 1 << 15
+    A = synth.rmat_csr(15, 16, seed=21, dtype=dtype, values="normal")
+    Bm = synth.varnnz_csr(n, n, 4, 32, 21, dtype, "normal", stream=3)
+    ub = oracle.rowub(_f64(A), _f64(Bm))
+    assert ub.max() > 20000 and (ub == 0).any()  # heavy rows and empty rows
+    ref, S = oracle.spgemm(_f64(A), _f64(Bm), with_abs=True)
+    got = B.spgemm(B.to_device(A), B.to_device(Bm)).to_host()
+    assert_same_csr(got, ref, S, dtype, what="R-MAT product")
+    bounds = synth.column_blocks(n, 8, n // 16, n // 4, 21)
+    pairs = synth.split_inner(A, Bm, bounds)
+    got = B.batched([(B.to_device(a), B.to_device(b)) for a, b in pairs]).to_host()
+    assert_same_csr(got, ref, S, dtype, what="R-MAT batched")
+
+
+def test_rmat_batched_full_size_sampled(B):
+    """The R-MAT batched workload at full size (scale 20, edge factor 16, B
+    with 4..32 uniform columns per row, 8 uneven inner blocks, FP32 N(0,1)):
+    row_ptr of the fused sum against the oracle's count on every row;
+    columns and values on the 16 heaviest rows and 2000 sampled ones."""
+    import ctypes as C
+    n = 1 << 20
+    A = synth.rmat_csr(20, 16, seed=20260324, dtype=np.float32, values="normal", stream=0)
+    Bm = synth.varnnz_csr(n, n, 4, 32, 20260324, np.float32, "normal", stream=1)
+    bounds = synth.column_blocks(n, 8, n // 16, n // 4, 20260324)
+    pairs = synth.split_inner(A, Bm, bounds)
+    got = B.batched([(B.to_device(a), B.to_device(b)) for a, b in pairs]).to_host()
+    Af, Bf = _f64(A), _f64(Bm)
+    ref_rp = np.zeros(n + 1, dtype=np.int64)
+    rc = oracle.lib().oracle_spgemm_count(
+        C.c_int64(n), C.c_int64(n), C.c_int64(n), Af.indptr.ctypes.data_as(C.c_void_p),
+        Af.indices.ctypes.data_as(C.c_void_p), Bf.indptr.ctypes.data_as(C.c_void_p),
+        Bf.indices.ctypes.data_as(C.c_void_p), ref_rp.ctypes.data_as(C.c_void_p))
+    assert rc == 0
+    assert np.array_equal(got.indptr.astype(np.int64), ref_rp)
+    ub = oracle.rowub(Af, Bf)
+    heavy = np.argsort(ub)[-16:]
+    rows = np.unique(np.concatenate([heavy, synth.rng_for(5, 5).choice(n, 2000, replace=False)]))
+    from helpers import row_subset
+    ref, S = oracle.spgemm(row_subset(Af, rows), Bf, with_abs=True)
+    assert_same_csr(row_subset(got, rows), ref, S, np.float32, what="R-MAT 2^20 sampled rows")
+
+
 def test_batched_equals_merge_of_products_exactly(B):
     pairs = [(synth.varnnz_csr(1500, 2000 + 100 * k, 0, 20, 40 + k, np.float64, "int", stream=0),
               synth.varnnz_csr(2000 + 100 * k, 2500, 0, 20, 40 + k, np.float64, "int", stream=1))
