@@ -73,12 +73,12 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
         a_row(P, i, as, ae);
         const SPG_GLOBAL int32_t *brp = gp(P.brp);
         int p = as;
-        for (; p + 4 <= ae; p += 4) {  // four independent gathers in flight
-          int r[4];
+        for (; p + 8 <= ae; p += 8) {  // eight independent gathers in flight
+          int r[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, i, p + u);
+          for (int u = 0; u < 8; ++u) r[u] = a_entry_row(P, i, p + u);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) key += brp[r[u] + 1] - brp[r[u]];
+          for (int u = 0; u < 8; ++u) key += brp[r[u] + 1] - brp[r[u]];
         }
         for (; p < ae; ++p) {
           const int r = a_entry_row(P, i, p);
@@ -100,7 +100,8 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
     if (lane_id() == 0) psum[threadIdx.x / kWave] = v;
   }
   __syncthreads();
-  if (threadIdx.x < kNB) blockhist[(int64_t)blockIdx.x * kNB + threadIdx.x] = hist[threadIdx.x];
+  // bin-major: blockhist[b * nblk + block]
+  if (threadIdx.x < kNB) blockhist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = hist[threadIdx.x];
   if (mode == 0 && threadIdx.x == 0) {
     long long s = 0;
     for (int w = 0; w < kBinBlock / kWave; ++w) s += psum[w];
@@ -109,36 +110,58 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
 }
 
 // Exclusive scan of the per-block histograms in bin-major order (one block
-// of 1024 threads): wave b owns bin b; each lane sums a contiguous range of
-// blocks, one wave scan turns the sums into range offsets, then the lane
-// writes its blocks' offsets.
+// of 1024 threads): wave b owns bin b, whose block counts are contiguous.
+// The wave reads them in coalesced chunks of 64, eight chunks in flight per
+// lane: one pass for the bin total, a second one (after the totals of all
+// bins give the bin's base) writing each block's offset.
 __global__ __launch_bounds__(1024) void k_binscan(int32_t *blockhist, int nblk, WsHeader *hdr) {
+  constexpr int U = 8;
   __shared__ int bintot[kNB];
-  const int b = threadIdx.x / kWave;   // 16 waves, one per bin
+  const int b = threadIdx.x / kWave;  // 16 waves, one per bin
   const int lane = lane_id();
-  const int per = (nblk + kWave - 1) / kWave;
-  const int lo = lane * per, hi = min(nblk, lo + per);
-  int sum = 0;
-  for (int k = lo; k < hi; ++k) sum += blockhist[(int64_t)k * kNB + b];
-  int x = sum;
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int y = __shfl_up(x, off);
-    if (lane >= off) x += y;
+  int32_t *h = blockhist + (int64_t)b * nblk;
+  int tot = 0;
+  for (int c0 = 0; c0 < nblk; c0 += kWave * U) {
+    int v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = c0 + u * kWave + lane;
+      v[u] = idx < nblk ? h[idx] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) tot += v[u];
   }
-  if (lane == kWave - 1) bintot[b] = x;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+  if (lane == 0) bintot[b] = tot;
   __syncthreads();
   int base = 0;
   for (int bb = 0; bb < b; ++bb) base += bintot[bb];
-  int run = base + x - sum;
-  for (int k = lo; k < hi; ++k) {
-    const int v = blockhist[(int64_t)k * kNB + b];
-    blockhist[(int64_t)k * kNB + b] = run;
-    run += v;
+  int carry = base;
+  for (int c0 = 0; c0 < nblk; c0 += kWave * U) {
+    int v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = c0 + u * kWave + lane;
+      v[u] = idx < nblk ? h[idx] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int x = v[u];
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+      }
+      const int idx = c0 + u * kWave + lane;
+      if (idx < nblk) h[idx] = carry + x - v[u];
+      carry += __shfl(x, kWave - 1);
+    }
   }
   if (lane == 0) {
-    hdr->bin_count[b] = bintot[b];
+    hdr->bin_count[b] = tot;
     hdr->bin_start[b] = base;
-    if (b == kNB - 1) hdr->bin_start[kNB] = base + bintot[b];
+    if (b == kNB - 1) hdr->bin_start[kNB] = base + tot;
   }
 }
 
@@ -159,7 +182,7 @@ __global__ __launch_bounds__(kBinBlock) void k_binscatter(const uint8_t *binid, 
   }
   __syncthreads();
   if (i < m) {
-    int off = blockoff[(int64_t)blockIdx.x * kNB + b];
+    int off = blockoff[(int64_t)b * gridDim.x + blockIdx.x];
     for (int ww = 0; ww < w; ++ww) off += wcnt[ww][b];
     rows[off + myrank] = i;
   }
