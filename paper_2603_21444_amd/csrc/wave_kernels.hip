@@ -44,31 +44,37 @@ __device__ __forceinline__ void enum_staged(const SPG_GLOBAL int32_t *bcol,
                                             const int *sb, const int *sl, const VT *sa, F &ins) {
   const int S = 1 << lS, ES = kWave >> lS, sg = lane >> lS, q0 = lane & (S - 1);
   for (int t0 = sg; t0 < nE; t0 += ES * U) {
-    int col[U];
-    VT v[U];
+    // all LDS reads first, then all global loads, then the products: no
+    // consumer sits between the U loads, so they are in flight together
+    int col[U], b0[U], len[U];
+    VT v[U], a[U], bv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int ee = t0 + ES * u;
+      const int ec = ee < nE ? ee : 0;
+      b0[u] = sb[ec];
+      len[u] = ee < nE ? sl[ec] : 0;
+      if (VALUES) a[u] = sa[ec];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
       col[u] = -1;
-      v[u] = VT(0);
-      if (ee < nE && q0 < sl[ee]) {
-        const int idx = sb[ee] + q0;
-        col[u] = bcol[idx];
-        if (VALUES) v[u] = sa[ee] * bval[idx];
+      bv[u] = VT(0);
+      if (q0 < len[u]) {
+        col[u] = bcol[b0[u] + q0];
+        if (VALUES) bv[u] = bval[b0[u] + q0];
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = VALUES ? a[u] * bv[u] : VT(0);
     ins.template batch<U>(col, v);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int ee = t0 + ES * u;
-      if (ee < nE) {
-        const int len = sl[ee];
-        for (int q = q0 + S; q < len; q += S) {
-          const int idx = sb[ee] + q;
-          int c1[1] = {bcol[idx]};
-          VT v1[1] = {VALUES ? sa[ee] * bval[idx] : VT(0)};
-          ins.template batch<1>(c1, v1);
-        }
+      for (int q = q0 + S; q < len[u]; q += S) {
+        const int idx = b0[u] + q;
+        int c1[1] = {bcol[idx]};
+        VT v1[1] = {VALUES ? a[u] * bval[idx] : VT(0)};
+        ins.template batch<1>(c1, v1);
       }
     }
   }
