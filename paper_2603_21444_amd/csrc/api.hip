@@ -115,7 +115,7 @@ WsLayout ws_layout(int64_t m, int64_t n, int heavy_slots) {
   o = align256(o + 8 * (size_t)nparts);
   L.heavy_slots = heavy_slots;
   L.heavyacc = o;
-  o = align256(o + (size_t)heavy_slots * (size_t)std::max<int64_t>(n, 1) * 8);
+  o = align256(o + (size_t)heavy_slots * (size_t)(std::max<int64_t>(n, 1) + 4) * 8);
   L.heavymap = o;  // used when a heavy row's bitmap does not fit in LDS
   o = align256(o + (size_t)heavy_slots * (size_t)((std::max<int64_t>(n, 1) + 31) / 32) * 4);
   L.total = o;

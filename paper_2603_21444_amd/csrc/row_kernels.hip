@@ -485,9 +485,10 @@ __global__ __launch_bounds__(1024) void k_sym_heavy(const Problem *__restrict__ 
 }
 
 // Numeric pass of heavy rows with the slot's dense accumulator in global
-// memory.  Pass 1 marks columns and zeroes the accumulator entries it marks
-// first, pass 2 adds the products, pass 3 walks the bitmap in column order,
-// so the output row comes out sorted.
+// memory.  One pass over the products marks each column in the bitmap and
+// adds the product into the accumulator; then the bitmap is walked in column
+// order (so the output row comes out sorted), and each accumulator entry read
+// is reset to zero for the slot's next row.
 template <bool LDSMAP, typename VT>
 __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ pr,
                                                     const int32_t *__restrict__ rows,
@@ -503,49 +504,73 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
   const int n = pr->n;
   const int nw = (n + 31) >> 5;
   uint32_t *map = LDSMAP ? reinterpret_cast<uint32_t *>(smem_raw) : gbitmap + (size_t)blockIdx.x * nw;
-  VT *acc = gacc + (size_t)blockIdx.x * n;
+  constexpr int VPV = 16 / sizeof(VT);  // values per 16-byte store
+  const size_t astride = (size_t)(n + VPV - 1) / VPV * VPV;  // 16-byte aligned slots
+  VT *acc = gacc + (size_t)blockIdx.x * astride;
   if (hdr->status) return;
   const int start = hdr->bin_start[blo];
   const int count = hdr->bin_start[kHeavyBin + 1] - start;
   const int tid = threadIdx.x;
   Stage<VT> st{sb, sl, sa};
+  if ((int)blockIdx.x >= count) return;
+  // The slot's dense accumulator is cleared once per launch; the output walk
+  // resets every entry it reads, so it is all zero again for the next row.
+  {
+    int4 *a4 = reinterpret_cast<int4 *>(acc);
+    const int n4 = (int)(astride / VPV);
+    for (int s = tid; s < n4; s += 1024) a4[s] = make_int4(0, 0, 0, 0);
+  }
   for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
     const int i = rows[start + ri];
     for (int w = tid; w < nw; w += 1024) map[w] = 0u;
+    // zeroed accumulator entries visible at device scope before the adds
     __threadfence();
     __syncthreads();
-    auto fmark = each_product([&](int col, VT) {
+    // one pass: mark the column, add the value
+    auto fadd = each_product([&](int col, VT v) {
       const uint32_t bit = 1u << (col & 31);
-      const uint32_t old = atomicOr(&map[col >> 5], bit);
-      if (!(old & bit)) acc[col] = VT(0);
+      if (!(map[col >> 5] & bit)) atomicOr(&map[col >> 5], bit);
+      global_add(&acc[col], v);
     });
-    for_each_product<true, false, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fmark);
-    // the accumulator lives in global memory: complete this pass's stores
-    // at device scope and drop stale L1 lines before the next pass
-    __threadfence();
-    __syncthreads();
-    auto fadd = each_product([&](int col, VT v) { global_add(&acc[col], v); });
     for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fadd);
+    // the adds complete at device scope; stale L1 lines are dropped
     __threadfence();
     __syncthreads();
     const int rs = crp[i];
     const int re = crp[i + 1];
     int pre = 0;
-    for (int w0 = 0; w0 < nw; w0 += 1024) {
-      const int w = w0 + tid;
-      const uint32_t bits = w < nw ? map[w] : 0u;
+    // the bitmap in chunks of 8 words per thread (8192 words per round)
+    for (int w0 = 0; w0 < nw; w0 += 8 * 1024) {
+      const int wb = w0 + 8 * tid;
+      uint32_t wd[8];
+      if (LDSMAP && wb + 8 <= nw) {  // two 16-byte LDS reads (the LDS bitmap is 16-byte aligned)
+        const uint4 x = reinterpret_cast<const uint4 *>(map + wb)[0];
+        const uint4 y = reinterpret_cast<const uint4 *>(map + wb)[1];
+        wd[0] = x.x; wd[1] = x.y; wd[2] = x.z; wd[3] = x.w;
+        wd[4] = y.x; wd[5] = y.y; wd[6] = y.z; wd[7] = y.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wd[j] = wb + j < nw ? map[wb + j] : 0u;
+      }
+      int cnt = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cnt += __popc(wd[j]);
       int tot;
-      int o = rs + pre + group_excl_scan<true, 1024>(__popc(bits), tid, wtot, tot);
-      uint32_t b = bits;
-      while (b) {
-        const int j = __ffs(b) - 1;
-        b &= b - 1;
-        const int col = (w << 5) + j;
-        if (o < re) {  // the symbolic count bounds the row (a changed pattern is flagged)
-          ccol[o] = col;
-          cval[o] = acc[col];
+      int o = rs + pre + group_excl_scan<true, 1024>(cnt, tid, wtot, tot);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        uint32_t bb = wd[j];
+        while (bb) {
+          const int col = ((wb + j) << 5) + __ffs(bb) - 1;
+          bb &= bb - 1;
+          const VT v = acc[col];
+          acc[col] = VT(0);
+          if (o < re) {  // the symbolic count bounds the row (a changed pattern is flagged)
+            ccol[o] = col;
+            cval[o] = v;
+          }
+          ++o;
         }
-        ++o;
       }
       pre += tot;
     }

@@ -218,14 +218,15 @@ struct Stage {
 // S) follow in a second loop.
 template <bool BLOCK, bool VALUES, int G, int U, typename VT, typename F>
 __device__ __forceinline__ void part_products(const Part &P, int i, bool active, int l, int lS,
-                                              Stage<VT> st, F &f) {
+                                              Stage<VT> st, F &f, int cfirst = 0,
+                                              int cstep = 1) {
   const SPG_GLOBAL int32_t *brp = gp(P.brp);
   const SPG_GLOBAL int32_t *bcol = gp(P.bcol);
   const SPG_GLOBAL VT *bval = gp(static_cast<const VT *>(P.bval));
   int as = 0, ae = 0;
   if (active) a_row(P, i, as, ae);
   const int nA = ae - as;
-  for (int c0 = 0; c0 < nA; c0 += G) {
+  for (int c0 = cfirst * G; c0 < nA; c0 += cstep * G) {
     const int e = c0 + l;
     if (e < nA) {
       int r;
@@ -289,9 +290,13 @@ __device__ __forceinline__ void part_products(const Part &P, int i, bool active,
 }
 
 // All products of row i of C = sum_k A_k B_k.  A row handled by a whole
-// block with K > 1 parts gives each of its waves its own parts (the parts'
-// chains of dependent loads then overlap instead of following each other);
-// the waves share the block's table and meet at one barrier at the end.
+// block with K > 1 parts lets its waves run independently on different
+// parts, so the parts' chains of dependent loads overlap instead of
+// following each other: wave w takes parts w, w + waves, ...  A 1024-lane
+// block with fewer parts than waves instead splits the parts' entries into
+// chunks of 64 and deals the (part, chunk) items out to the waves, so that
+// none idles.  The waves share the block's table and meet at one barrier at
+// the end.
 template <bool BLOCK, bool VALUES, int G, int U, typename VT, typename F>
 __device__ __forceinline__ void for_each_product(const Problem *__restrict__ pr, int i,
                                                  bool active, int l, int lS, Stage<VT> st,
@@ -301,8 +306,41 @@ __device__ __forceinline__ void for_each_product(const Problem *__restrict__ pr,
     constexpr int NWV = G / kWave;
     const int w = l / kWave, lw = l % kWave;
     Stage<VT> sw{st.b0 + w * kWave, st.len + w * kWave, VALUES ? st.a + w * kWave : st.a};
-    for (int k = w; k < K; k += NWV)
-      part_products<false, VALUES, kWave, U, VT>(pr->part[k], i, active, lw, lS, sw, f);
+    // every wave has a part of its own (or the block is small): wave w takes
+    // parts w, w + NWV, ...  Only the 1024-lane kernels carry the split
+    // below; it costs the smaller ones more in code than it saves.
+    if (G < 1024 || K >= NWV) {
+      for (int k = w; k < K; k += NWV)
+        part_products<false, VALUES, kWave, U, VT>(pr->part[k], i, active, lw, lS, sw, f);
+      group_sync<true>();
+      return;
+    }
+    if constexpr (G >= 1024) {
+      // wave w takes items w, w + NWV, ...: item j is chunk c of part k, with
+      // the items numbered part by part.  Lane k < K holds part k's chunk
+      // count; an inclusive wave scan gives the first item after each part.
+      int nc = 0;
+      if (lw < K) {
+        int as = 0, ae = 0;
+        if (active) a_row(pr->part[lw], i, as, ae);
+        nc = (ae - as + kWave - 1) / kWave;
+      }
+      int incl = nc;
+#pragma unroll
+      for (int off = 1; off < SPG_MAX_PARTS; off <<= 1) {
+        const int y = __shfl_up(incl, off);
+        if (lw >= off) incl += y;
+      }
+      const int total = __shfl(incl, K - 1);
+      for (int j = w; j < total; j += NWV) {
+        // part of item j: the number of parts whose items all precede j
+        // wave-uniform: keeps the part's pointers in scalar registers
+        const int k = __builtin_amdgcn_readfirstlane(__popcll(__ballot(lw < K && incl <= j)));
+        const int before = __builtin_amdgcn_readfirstlane(k > 0 ? __shfl(incl, k - 1) : 0);
+        part_products<false, VALUES, kWave, U, VT>(pr->part[k], i, active, lw, lS, sw, f,
+                                                   j - before, 1 << 24);
+      }
+    }
     group_sync<true>();
     return;
   }
