@@ -64,10 +64,18 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   const int m = pr->m;
   const int i = blockIdx.x * kBinBlock + threadIdx.x;
   int64_t key = 0;
+  bool longrow = false;
   if (i < m) {
     if (mode == 0) {
       const int K = pr->K;
+      int len = 0;
       for (int k = 0; k < K; ++k) {
+        int as, ae;
+        a_row(pr->part[k], i, as, ae);
+        len += ae - as;
+      }
+      longrow = len > kWave;  // counted by the whole wave below
+      for (int k = 0; k < K && !longrow; ++k) {
         const Part &P = pr->part[k];
         int as, ae;
         a_row(P, i, as, ae);
@@ -85,10 +93,43 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
           key += brp[r + 1] - brp[r];
         }
       }
-      if (key == 0) cnt_zero[i] = 0;
     } else {
       key = crp[i + 1] - crp[i];
     }
+  }
+  if (mode == 0) {
+    // rows with more than 64 entries: the wave sums their products together
+    uint64_t pend = __ballot(longrow);
+    while (pend) {
+      const int lead = __ffsll((unsigned long long)pend) - 1;
+      pend &= pend - 1;
+      const int ri = __shfl(i, lead);
+      int64_t part = 0;
+      for (int k = 0; k < pr->K; ++k) {
+        const Part &P = pr->part[k];
+        int as, ae;
+        a_row(P, ri, as, ae);
+        const SPG_GLOBAL int32_t *brp = gp(P.brp);
+        int p = as + lane_id();
+        for (; p + 3 * kWave < ae; p += 4 * kWave) {  // four gathers in flight per lane
+          int r[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, ri, p + u * kWave);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) part += brp[r[u] + 1] - brp[r[u]];
+        }
+        for (; p < ae; p += kWave) {
+          const int r = a_entry_row(P, ri, p);
+          part += brp[r + 1] - brp[r];
+        }
+      }
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+      if (lane_id() == lead) key = part;
+    }
+  }
+  if (i < m) {
+    if (mode == 0 && key == 0) cnt_zero[i] = 0;
     int b = bin_of(key, maxbin);
     binid[i] = (uint8_t)b;
     atomicAdd(&hist[b], 1);
