@@ -394,6 +394,233 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_wave(
 }
 
 // ---------------------------------------------------------------------------
+// Numeric pass by bucketing (rows of at most 256 distinct columns, n <= 2^24).
+//
+// Instead of a hash table with probing, every product is dropped into the
+// bucket of its order-preserving home slot floor(col * T / n) (buckets are
+// in column order), taking a ticket from the bucket's counter with one
+// integer LDS atomic; the product is staged in LDS with its ticket.  A wave
+// scan of the T counters gives each bucket's start, every product moves to
+// start + ticket, each (small) bucket is sorted in place by column, and the
+// row is then in column order: the first of each run of equal columns sums
+// the run and writes it, at a rank given by one ballot per 64 positions.
+// There are no probe loops, no compare-and-swap retries and no rank-counter
+// walks, which is where the hash kernel spends its scalar instructions.
+// Rows with more products than the staging area holds, or a bucket with more
+// than 255 products, go to the sort-based fallback kernel.
+constexpr int kBucketMaxJ = 6;  // staged products per lane (capacity 384)
+
+template <typename VT>
+struct BucketInsert {
+  uint32_t *cnt;   // T/2 words: two 16-bit bucket counters per word
+  uint32_t *ikey;  // [cap] col | ticket << 24
+  VT *ival;        // [cap]
+  int *wcount;     // products staged so far (LDS, per wave)
+  uint32_t mul;
+  int cap;
+  bool over;
+  template <int N>
+  __device__ __forceinline__ void batch(const int (&col)[N], const VT (&v)[N]) {
+    uint32_t old[N], sh[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const uint32_t b = mono_slot((uint32_t)col[u], mul);
+      sh[u] = (b & 1u) << 4;
+      old[u] = col[u] >= 0 ? atomicAdd(&cnt[b >> 1], 1u << sh[u]) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      // staging index: one LDS atomic per wave and call (correct for any set
+      // of active lanes, also inside divergent code)
+      const bool valid = col[u] >= 0;
+      const uint64_t m = __ballot(valid);
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int p0 = 0;
+      if (m != 0 && lane_id() == leader) p0 = atomicAdd(wcount, __popcll(m));
+      p0 = __shfl(p0, leader < 0 ? 0 : leader);
+      const int p = p0 + __popcll(m & lanes_below());
+      const uint32_t t = (old[u] >> sh[u]) & 0xffffu;
+      if (valid) {
+        if (p < cap && t < 256u) {
+          ikey[p] = (uint32_t)col[u] | (t << 24);
+          ival[p] = v[u];
+        } else {
+          over = true;
+        }
+      }
+    }
+  }
+};
+
+template <typename VT>
+__global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_bucket(
+    const Problem *__restrict__ pr, const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
+    int bin, int lS, int T, int cap, uint32_t mul, const int32_t *__restrict__ crp,
+    int32_t *__restrict__ ccol, VT *__restrict__ cval, int32_t *__restrict__ fb_rows) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int wcount[4];
+  const int w = ufl(threadIdx.x / kWave), lane = lane_id();
+  const int TW = T / 2;  // counter words per wave
+  uint32_t *cnt_all = reinterpret_cast<uint32_t *>(smem_raw);
+  uint32_t *ikey_all = cnt_all + 4 * TW;
+  VT *ival_all = reinterpret_cast<VT *>(ikey_all + 4 * cap);
+  int *sb_all = reinterpret_cast<int *>(ival_all + 4 * cap);
+  int *sl_all = sb_all + 4 * kWave;
+  VT *sa_all = reinterpret_cast<VT *>(sl_all + 4 * kWave);
+  uint32_t *cnt = cnt_all + w * TW;
+  uint32_t *ikey = ikey_all + w * cap;
+  VT *ival = ival_all + w * cap;
+  int *sb = sb_all + w * kWave;
+  int *sl = sl_all + w * kWave;
+  VT *sa = sa_all + w * kWave;
+  if (hdr->status) return;
+  const int count = hdr->bin_count[bin];
+  const int start = hdr->bin_start[bin];
+  const int stride = gridDim.x * 4;
+  const Part &P0 = pr->part[0];
+  const uint64_t below = lanes_below();
+  const int wpl = TW / kWave;  // counter words per lane (T >= 128)
+  int ri = blockIdx.x * 4 + w;
+  NextRow<VT> n1, n2, n3;
+  n1.link_row(rows, start, ri, count);
+  n1.link_ptrs(P0, crp);
+  n1.template link_entry<true>(P0, lane);
+  RowHead<VT> cur = n1.link_b(P0);
+  n1.link_row(rows, start, ri + stride, count);
+  n1.link_ptrs(P0, crp);
+  n2.link_row(rows, start, ri + 2 * stride, count);
+  for (; ri < count; ri += stride) {
+    {
+      int4 *c4 = reinterpret_cast<int4 *>(cnt);
+      for (int s = lane; s < TW / 4; s += kWave) c4[s] = make_int4(0, 0, 0, 0);
+    }
+    if (lane == 0) wcount[w] = 0;
+    group_sync<false>();
+    n1.template link_entry<true>(P0, lane);
+    BucketInsert<VT> ins{cnt, ikey, ival, &wcount[w], mul, cap, false};
+    row_products<true, kWU, VT>(pr, cur, lane, lS, sb, sl, sa, ins);
+    const RowHead<VT> nh = n1.link_b(P0);
+    n2.link_ptrs(P0, crp);
+    n3.link_row(rows, start, ri + 3 * stride, count);
+    const int P = ufl(wcount[w]);
+    const int nnz = cur.re - cur.rs;
+    if (__any(ins.over) || P > cap) {  // staging overflow: the fallback redoes this row
+      if (lane == 0) fb_rows[atomicAdd(&hdr->fallback_count, 1)] = cur.i;
+      group_sync<false>();
+      cur = nh;
+      n1 = n2;
+      n2 = n3;
+      continue;
+    }
+    // 1. bucket starts: exclusive scan of the 16-bit counters, in place
+    {
+      uint32_t wv[4];
+      int loc = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        wv[j] = j < wpl ? cnt[lane * wpl + j] : 0u;
+        loc += (int)(wv[j] & 0xffffu) + (int)(wv[j] >> 16);
+      }
+      int x = loc;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+      }
+      int run = x - loc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j < wpl) {
+          const uint32_t lo = (uint32_t)run;
+          run += (int)(wv[j] & 0xffffu);
+          const uint32_t hi = (uint32_t)run;
+          run += (int)(wv[j] >> 16);
+          cnt[lane * wpl + j] = lo | (hi << 16);
+        }
+      }
+    }
+    // 2. every product to start[bucket] + ticket
+    uint32_t kk[kBucketMaxJ];
+    VT vv[kBucketMaxJ];
+#pragma unroll
+    for (int j = 0; j < kBucketMaxJ; ++j) {
+      const int p = lane + j * kWave;
+      kk[j] = p < P ? ikey[p] : 0u;
+      vv[j] = p < P ? ival[p] : VT(0);
+    }
+    group_sync<false>();
+#pragma unroll
+    for (int j = 0; j < kBucketMaxJ; ++j) {
+      if (lane + j * kWave < P) {
+        const uint32_t c = kk[j] & 0xffffffu;
+        const uint32_t b = mono_slot(c, mul);
+        const int st0 = (int)((cnt[b >> 1] >> ((b & 1u) << 4)) & 0xffffu);
+        const int pos = st0 + (int)(kk[j] >> 24);
+        ikey[pos] = c;
+        ival[pos] = vv[j];
+      }
+    }
+    group_sync<false>();
+    // 3. sort every bucket of two or more products by column (insertion sort)
+    for (int b = lane; b < T; b += kWave) {
+      const int s0 = (int)((cnt[b >> 1] >> ((b & 1) << 4)) & 0xffffu);
+      const int s1 = b + 1 < T ? (int)((cnt[(b + 1) >> 1] >> (((b + 1) & 1) << 4)) & 0xffffu) : P;
+      for (int q = s0 + 1; q < s1; ++q) {
+        const uint32_t kq = ikey[q];
+        const VT vq = ival[q];
+        int r = q - 1;
+        while (r >= s0 && ikey[r] > kq) {
+          ikey[r + 1] = ikey[r];
+          ival[r + 1] = ival[r];
+          --r;
+        }
+        ikey[r + 1] = kq;
+        ival[r + 1] = vq;
+      }
+    }
+    group_sync<false>();
+    // 4. runs of equal columns: the first of each run sums it and writes
+    SPG_GLOBAL int32_t *cb = gpw(ccol) + cur.rs;
+    SPG_GLOBAL VT *vb = gpw(cval) + cur.rs;
+    int base = 0;
+    for (int p0 = 0; p0 < P; p0 += kWave) {
+      const int p = p0 + lane;
+      const uint32_t c = p < P ? ikey[p] : 0xffffffffu;
+      const uint32_t cp = p > 0 && p < P ? ikey[p - 1] : 0xfffffffeu;
+      const bool first = p < P && c != cp;
+      const uint64_t m = __ballot(first);
+      if (first) {
+        VT sum = ival[p];
+        for (int q = p + 1; q < P && ikey[q] == c; ++q) sum += ival[q];
+        const int d = base + __popcll(m & below);
+        if (d < nnz) {  // the symbolic count bounds the row (a changed pattern is flagged)
+          cb[d] = (int)c;
+          vb[d] = sum;
+        }
+      }
+      base += __popcll(m);
+    }
+    if (lane == 0 && base != nnz) atomicOr(&hdr->status, kStatInvalid);
+    group_sync<false>();
+    cur = nh;
+    n1 = n2;
+    n2 = n3;
+  }
+}
+
+// Staging capacity and LDS of the bucket kernel for bin b (T = 2 * edge
+// buckets, 1.5 * edge staged products).
+int bucket_cap(int b) { return (8 << b) + (4 << b); }
+bool bucket_ok(int b) {
+  const int T = bin_slots(b);
+  return T >= 128 && T <= 512 && bucket_cap(b) <= kBucketMaxJ * kWave;
+}
+size_t bucket_lds_bytes(int b, size_t vbytes) {
+  return (size_t)4 * (bin_slots(b) / 2) * 4 + (size_t)4 * bucket_cap(b) * (4 + vbytes) +
+         (size_t)4 * kWave * (8 + vbytes);
+}
+
+// ---------------------------------------------------------------------------
 
 size_t sym_wave_lds_bytes(int b) { return (size_t)4 * bin_slots(b) * 4 + (size_t)8 * kWave * 4; }
 
@@ -435,6 +662,13 @@ template <typename VT>
 void launch_num_wave_t(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin, int lS,
                        int count, uint32_t mul, int maxwin, bool pack, const int32_t *crp,
                        int32_t *ccol, VT *cval, int32_t *fb, hipStream_t st) {
+  if (pack && bucket_ok(bin)) {
+    const size_t lds = bucket_lds_bytes(bin, sizeof(VT));
+    const int grid = wave_grid(count, lds, 4 * SPG_WAVE_WAVES);
+    hipLaunchKernelGGL((k_num_bucket<VT>), dim3(grid), dim3(256), lds, st, dpr, rows, hdr, bin, lS,
+                       bin_slots(bin), bucket_cap(bin), mul, crp, ccol, cval, fb);
+    return;
+  }
   const int TT = num_wave_slots(bin);
   const size_t lds = num_wave_lds_bytes(bin, sizeof(VT), pack);
   const int grid = wave_grid(count, lds, 4 * SPG_WAVE_WAVES);
@@ -464,6 +698,8 @@ hipError_t configure_wave_lds(size_t lds_max) {
       reinterpret_cast<const void *>(&k_num_wave<float, false>),
       reinterpret_cast<const void *>(&k_num_wave<double, true>),
       reinterpret_cast<const void *>(&k_num_wave<double, false>),
+      reinterpret_cast<const void *>(&k_num_bucket<float>),
+      reinterpret_cast<const void *>(&k_num_bucket<double>),
   };
   for (const void *k : ks) {
     hipError_t e =
