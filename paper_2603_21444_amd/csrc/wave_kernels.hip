@@ -400,10 +400,13 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_wave(
 // bucket of its order-preserving home slot floor(col * T / n) (buckets are
 // in column order), taking a ticket from the bucket's counter with one
 // integer LDS atomic; the product is staged in LDS with its ticket.  A wave
-// scan of the T counters gives each bucket's start, every product moves to
-// start + ticket, each (small) bucket is sorted in place by column, and the
-// row is then in column order: the first of each run of equal columns sums
-// the run and writes it, at a rank given by one ballot per 64 positions.
+// scan of the T counters gives each bucket's start and every product moves
+// to start + ticket.  A row without repeated columns (as many products as
+// output entries, known from the symbolic pass) then writes each product at
+// its bucket's start plus the number of smaller columns in the bucket; other
+// rows sort each (small) bucket in place by column, and the first of each
+// run of equal columns sums the run and writes it, at a rank given by one
+// ballot per 64 positions.
 // There are no probe loops, no compare-and-swap retries and no rank-counter
 // walks, which is where the hash kernel spends its scalar instructions.
 // Rows with more products than the staging area holds, or a bucket with more
@@ -428,19 +431,27 @@ struct BucketInsert {
       sh[u] = (b & 1u) << 4;
       old[u] = col[u] >= 0 ? atomicAdd(&cnt[b >> 1], 1u << sh[u]) : 0u;
     }
+    // staging indices: one LDS atomic per wave and call (correct for any set
+    // of active lanes, also inside divergent code)
+    uint64_t m[N];
+    int tot = 0;
 #pragma unroll
     for (int u = 0; u < N; ++u) {
-      // staging index: one LDS atomic per wave and call (correct for any set
-      // of active lanes, also inside divergent code)
-      const bool valid = col[u] >= 0;
-      const uint64_t m = __ballot(valid);
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      int p0 = 0;
-      if (m != 0 && lane_id() == leader) p0 = atomicAdd(wcount, __popcll(m));
-      p0 = __shfl(p0, leader < 0 ? 0 : leader);
-      const int p = p0 + __popcll(m & lanes_below());
+      m[u] = __ballot(col[u] >= 0);
+      tot += __popcll(m[u]);
+    }
+    const uint64_t act = __ballot(true);
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    int p0 = 0;
+    if (tot > 0 && lane_id() == leader) p0 = atomicAdd(wcount, tot);
+    p0 = __shfl(p0, leader);
+    const uint64_t below = lanes_below();
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const int p = p0 + __popcll(m[u] & below);
+      p0 += __popcll(m[u]);
       const uint32_t t = (old[u] >> sh[u]) & 0xffffu;
-      if (valid) {
+      if (col[u] >= 0) {
         if (p < cap && t < 256u) {
           ikey[p] = (uint32_t)col[u] | (t << 24);
           ival[p] = v[u];
@@ -560,6 +571,30 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_bucket(
         ival[pos] = vv[j];
       }
     }
+    SPG_GLOBAL int32_t *cb = gpw(ccol) + cur.rs;
+    SPG_GLOBAL VT *vb = gpw(cval) + cur.rs;
+    if (P == nnz) {
+      // no repeated column: a product's rank is its bucket's start plus the
+      // number of smaller columns in the (small) bucket
+      group_sync<false>();
+      for (int p = lane; p < P; p += kWave) {
+        const uint32_t c = ikey[p];
+        const uint32_t b = mono_slot(c, mul);
+        const int s0 = (int)((cnt[b >> 1] >> ((b & 1u) << 4)) & 0xffffu);
+        const int s1 = b + 1 < (uint32_t)T
+                           ? (int)((cnt[(b + 1) >> 1] >> (((b + 1) & 1u) << 4)) & 0xffffu)
+                           : P;
+        int r = s0;
+        for (int q = s0; q < s1; ++q) r += ikey[q] < c ? 1 : 0;
+        cb[r] = (int)c;
+        vb[r] = ival[p];
+      }
+      group_sync<false>();
+      cur = nh;
+      n1 = n2;
+      n2 = n3;
+      continue;
+    }
     group_sync<false>();
     // 3. sort every bucket of two or more products by column (insertion sort)
     for (int b = lane; b < T; b += kWave) {
@@ -580,8 +615,6 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_bucket(
     }
     group_sync<false>();
     // 4. runs of equal columns: the first of each run sums it and writes
-    SPG_GLOBAL int32_t *cb = gpw(ccol) + cur.rs;
-    SPG_GLOBAL VT *vb = gpw(cval) + cur.rs;
     int base = 0;
     for (int p0 = 0; p0 < P; p0 += kWave) {
       const int p = p0 + lane;
