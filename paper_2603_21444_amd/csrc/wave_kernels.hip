@@ -20,11 +20,15 @@ namespace spg {
 #ifndef SPG_WAVE_UNROLL
 #define SPG_WAVE_UNROLL 2
 #endif
+#ifndef SPG_SYMW_UNROLL
+#define SPG_SYMW_UNROLL 1
+#endif
 #ifndef SPG_WAVE_WAVES
 #define SPG_WAVE_WAVES 8
 #endif
 
-constexpr int kWU = SPG_WAVE_UNROLL;
+constexpr int kWU = SPG_WAVE_UNROLL;   // products per lane per batch, numeric
+constexpr int kSWU = SPG_SYMW_UNROLL;  // the same for the symbolic count
 
 __device__ __forceinline__ int ufl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -246,7 +250,7 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_sym_wave(
     group_sync<false>();
     n1.template link_entry<false>(P0, lane);
     WSymInsert ins{tab, T, log2T, 0};
-    row_products<false, kWU, float>(pr, cur, lane, lS, sb, sl, nullptr, ins);
+    row_products<false, kSWU, float>(pr, cur, lane, lS, sb, sl, nullptr, ins);
     const RowHead<float> nh = n1.link_b(P0);
     n2.link_ptrs(P0, nullptr);
     n3.link_row(rows, start, ri + 3 * stride, count);
