@@ -347,6 +347,228 @@ __global__ __launch_bounds__(Geom<G>::WG, num_waves<G>()) void k_num_rows(const 
   }
 }
 
+// Numeric pass of a block-group bin by bucketing (one row per block of G
+// lanes, n <= 2^24): the bucket scheme of the one-row-per-wave kernel
+// (tickets in the bucket of the order-preserving home slot, scan,
+// placement), here with T = edge buckets and 1.125 edge staged products so
+// that three rows of the 2^12-column bin fit one CU's LDS (the hash table
+// needs 16 bytes per column, this 11).  Rows without repeated columns rank
+// each product inside its bucket; other rows sort the buckets and give each
+// thread a contiguous range of positions, whose run starts one block scan
+// turns into output ranks.  Overflowing rows go to the fallback kernel.
+constexpr int kBktJ = 12;  // staged products per thread at most
+
+template <typename VT>
+struct BucketInsertB {
+  uint32_t *cnt;   // T/2 words: two 16-bit bucket counters per word
+  uint32_t *ikey;  // [cap] col | ticket << 24
+  VT *ival;        // [cap]
+  int *wcount;     // products staged so far (LDS, per block)
+  uint32_t mul;
+  int cap;
+  bool over;
+  template <int N>
+  __device__ __forceinline__ void batch(const int (&col)[N], const VT (&v)[N]) {
+    uint32_t old[N], sh[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const uint32_t b = mono_slot((uint32_t)col[u], mul);
+      sh[u] = (b & 1u) << 4;
+      old[u] = col[u] >= 0 ? atomicAdd(&cnt[b >> 1], 1u << sh[u]) : 0u;
+    }
+    uint64_t m[N];
+    int tot = 0;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      m[u] = __ballot(col[u] >= 0);
+      tot += __popcll(m[u]);
+    }
+    const uint64_t act = __ballot(true);
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    int p0 = 0;
+    if (tot > 0 && lane_id() == leader) p0 = atomicAdd(wcount, tot);
+    p0 = __shfl(p0, leader);
+    const uint64_t below = lanes_below();
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const int p = p0 + __popcll(m[u] & below);
+      p0 += __popcll(m[u]);
+      const uint32_t t = (old[u] >> sh[u]) & 0xffffu;
+      if (col[u] >= 0) {
+        if (p < cap && t < 256u) {
+          ikey[p] = (uint32_t)col[u] | (t << 24);
+          ival[p] = v[u];
+        } else {
+          over = true;
+        }
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ int bkt_start(const uint32_t *cnt, uint32_t b) {
+  return (int)((cnt[b >> 1] >> ((b & 1u) << 4)) & 0xffffu);
+}
+
+template <int G, typename VT>
+__global__ __launch_bounds__(G) void k_num_bucket_blk(
+    const Problem *__restrict__ pr, const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
+    int bin, int lS, int T, int cap, uint32_t mul, const int32_t *__restrict__ crp,
+    int32_t *__restrict__ ccol, VT *__restrict__ cval, int32_t *__restrict__ fb_rows) {
+  static_assert(G >= 128 && G <= 1024, "block groups only");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int wcount, overflow;
+  __shared__ int wtot[G / kWave];
+  const int tid = threadIdx.x;
+  const int TW = T / 2;
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(smem_raw);
+  uint32_t *ikey = cnt + TW;
+  VT *ival = reinterpret_cast<VT *>(ikey + cap);
+  int *sb = reinterpret_cast<int *>(ival + cap);
+  int *sl = sb + G;
+  VT *sa = reinterpret_cast<VT *>(sl + G);
+  Stage<VT> st{sb, sl, sa};
+  if (hdr->status) return;
+  const int count = hdr->bin_count[bin];
+  const int start = hdr->bin_start[bin];
+  const int wpt = (TW + G - 1) / G;  // counter words per thread
+  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+    const int i = __builtin_amdgcn_readfirstlane(rows[start + ri]);
+    const int rs = crp[i];
+    const int nnz = crp[i + 1] - rs;
+    for (int s = tid; s < TW; s += G) cnt[s] = 0u;
+    if (tid == 0) {
+      wcount = 0;
+      overflow = 0;
+    }
+    __syncthreads();
+    BucketInsertB<VT> ins{cnt, ikey, ival, &wcount, mul, cap, false};
+    for_each_product<true, true, G, kUnroll, VT>(pr, i, true, tid, lS, st, ins);
+    if (ins.over) overflow = 1;
+    __syncthreads();
+    const int P = wcount;
+    if (overflow || P > cap) {  // the fallback redoes this row
+      if (tid == 0) fb_rows[atomicAdd(&hdr->fallback_count, 1)] = i;
+      __syncthreads();
+      continue;
+    }
+    // 1. bucket starts: exclusive scan of the 16-bit counters, in place
+    {
+      const int w0 = tid * wpt;
+      int loc = 0;
+      for (int j = 0; j < wpt; ++j) {
+        if (w0 + j < TW) {
+          const uint32_t wv = cnt[w0 + j];
+          loc += (int)(wv & 0xffffu) + (int)(wv >> 16);
+        }
+      }
+      int total;
+      int run = group_excl_scan<true, G>(loc, tid, wtot, total);
+      for (int j = 0; j < wpt; ++j) {
+        if (w0 + j < TW) {
+          const uint32_t wv = cnt[w0 + j];
+          const uint32_t lo = (uint32_t)run;
+          run += (int)(wv & 0xffffu);
+          const uint32_t hi = (uint32_t)run;
+          run += (int)(wv >> 16);
+          cnt[w0 + j] = lo | (hi << 16);
+        }
+      }
+    }
+    __syncthreads();
+    // 2. every product to start[bucket] + ticket
+    {
+      uint32_t kk[kBktJ];
+      VT vv[kBktJ];
+#pragma unroll
+      for (int j = 0; j < kBktJ; ++j) {
+        const int p = tid + j * G;
+        kk[j] = p < P ? ikey[p] : 0u;
+        vv[j] = p < P ? ival[p] : VT(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kBktJ; ++j) {
+        if (tid + j * G < P) {
+          const uint32_t c = kk[j] & 0xffffffu;
+          const int pos = bkt_start(cnt, mono_slot(c, mul)) + (int)(kk[j] >> 24);
+          ikey[pos] = c;
+          ival[pos] = vv[j];
+        }
+      }
+    }
+    __syncthreads();
+    SPG_GLOBAL int32_t *cb = gpw(ccol) + rs;
+    SPG_GLOBAL VT *vb = gpw(cval) + rs;
+    if (P == nnz) {
+      // no repeated column: bucket start + smaller columns in the bucket
+      for (int p = tid; p < P; p += G) {
+        const uint32_t c = ikey[p];
+        const uint32_t b = mono_slot(c, mul);
+        const int s0 = bkt_start(cnt, b);
+        const int s1 = b + 1 < (uint32_t)T ? bkt_start(cnt, b + 1) : P;
+        int r = s0;
+        for (int q = s0; q < s1; ++q) r += ikey[q] < c ? 1 : 0;
+        cb[r] = (int)c;
+        vb[r] = ival[p];
+      }
+      __syncthreads();
+      continue;
+    }
+    // 3. sort every bucket of two or more products by column
+    for (int b = tid; b < T; b += G) {
+      const int s0 = bkt_start(cnt, (uint32_t)b);
+      const int s1 = b + 1 < T ? bkt_start(cnt, (uint32_t)b + 1) : P;
+      for (int q = s0 + 1; q < s1; ++q) {
+        const uint32_t kq = ikey[q];
+        const VT vq = ival[q];
+        int r = q - 1;
+        while (r >= s0 && ikey[r] > kq) {
+          ikey[r + 1] = ikey[r];
+          ival[r + 1] = ival[r];
+          --r;
+        }
+        ikey[r + 1] = kq;
+        ival[r + 1] = vq;
+      }
+    }
+    __syncthreads();
+    // 4. each thread a contiguous range of positions: its run starts, one
+    //    block scan, then the first of each run sums the run and writes it
+    {
+      const int per = (P + G - 1) / G;
+      const int p0 = tid * per, p1 = min(P, p0 + per);
+      int firsts = 0;
+      for (int p = p0; p < p1; ++p) firsts += (p == 0 || ikey[p] != ikey[p - 1]) ? 1 : 0;
+      int total;
+      int d = group_excl_scan<true, G>(firsts, tid, wtot, total);
+      for (int p = p0; p < p1; ++p) {
+        const uint32_t c = ikey[p];
+        if (p == 0 || c != ikey[p - 1]) {
+          VT sum = ival[p];
+          for (int q = p + 1; q < P && ikey[q] == c; ++q) sum += ival[q];
+          if (d < nnz) {  // the symbolic count bounds the row (a changed pattern is flagged)
+            cb[d] = (int)c;
+            vb[d] = sum;
+          }
+          ++d;
+        }
+      }
+      if (tid == 0 && total != nnz) atomicOr(&hdr->status, kStatInvalid);
+    }
+    __syncthreads();
+  }
+}
+
+// Bins the block bucket kernel serves: n <= 2^24 and edge(b) * 9/8 staged
+// products within kBktJ per thread.
+int bucket_blk_cap(int b) { return (8 << b) + (1 << b); }
+bool bucket_blk_ok(int b, int G) { return G >= 128 && bucket_blk_cap(b) <= kBktJ * G; }
+size_t bucket_blk_lds(int b, int G, size_t vbytes) {
+  const size_t T = (size_t)(8 << b);
+  return T * 2 + (size_t)bucket_blk_cap(b) * (4 + vbytes) + (size_t)G * (8 + vbytes);
+}
+
 // Fallback numeric pass: scrambled LDS hash, in-place compaction, bitonic
 // sort of (column, value) pairs, coalesced write.  One row per block.
 template <typename VT>
@@ -747,6 +969,30 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
                       sizeof(VT) == 8, fb, st);
       continue;
     }
+    if (pack && G > kWave && bucket_blk_ok(b, G) &&
+        bucket_blk_lds(b, G, sizeof(VT)) <= D.lds_per_block) {
+      const size_t lds = bucket_blk_lds(b, G, sizeof(VT));
+      const int grid = grid_for(bins_count(bp, b, b), 1, D.cus * blocks_per_cu(lds, G, D.lds_per_cu));
+      const int T = 8 << b;
+      const uint32_t mul = mono_mul(T, bp.n);
+      const int lS = sub_log2(bp, b, G);
+      const int cap = bucket_blk_cap(b);
+      switch (G) {
+#define SPG_BKT_CASE(g)                                                                        \
+  case g:                                                                                      \
+    hipLaunchKernelGGL((k_num_bucket_blk<g, VT>), dim3(grid), dim3(g), lds, st, dpr, rows, hdr, \
+                       b, lS, T, cap, mul, crp, ccol, cval, fb);                               \
+    break;
+        SPG_BKT_CASE(128)
+        SPG_BKT_CASE(256)
+        SPG_BKT_CASE(512)
+        default:
+          hipLaunchKernelGGL((k_num_bucket_blk<1024, VT>), dim3(grid), dim3(1024), lds, st, dpr,
+                             rows, hdr, b, lS, T, cap, mul, crp, ccol, cval, fb);
+#undef SPG_BKT_CASE
+      }
+      continue;
+    }
     while (G < 1024 && num_lds_bytes(b, G, sizeof(VT), pack) > D.lds_per_block) G *= 2;
     const int WG = wg_for(G);
     const int R = WG / G;
@@ -805,6 +1051,12 @@ static void num_kernels(std::vector<const void *> &ks) {
   ks.push_back(reinterpret_cast<const void *>(&k_num_rows<256, VT, PACK>));
   ks.push_back(reinterpret_cast<const void *>(&k_num_rows<512, VT, PACK>));
   ks.push_back(reinterpret_cast<const void *>(&k_num_rows<1024, VT, PACK>));
+  if (PACK) {
+    ks.push_back(reinterpret_cast<const void *>(&k_num_bucket_blk<128, VT>));
+    ks.push_back(reinterpret_cast<const void *>(&k_num_bucket_blk<256, VT>));
+    ks.push_back(reinterpret_cast<const void *>(&k_num_bucket_blk<512, VT>));
+    ks.push_back(reinterpret_cast<const void *>(&k_num_bucket_blk<1024, VT>));
+  }
 }
 
 hipError_t configure_lds_limits(size_t lds_max) {
