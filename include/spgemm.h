@@ -97,10 +97,12 @@ int spgemm_plan_info(spg_plan plan, int64_t *nnz, int64_t *products);
 
 const char *spgemm_status_string(int status);
 
-/* Rows per bin after an eager symbolic call (host arrays of SPG_NBINS):
- * bins by products per row (symbolic pass) and by nnz per row (numeric
- * pass).  Bin b >= 1 holds rows with key in (8*2^(b-1), 8*2^b] (bin 1:
- * 1..16), bin 0 empty rows, bin 12 the rows beyond every LDS table.
+/* Rows per bin after an eager symbolic call (host arrays of SPG_NBINS),
+ * bins by products per row.  The numeric pass reuses the symbolic bins (a
+ * row's products bound its nnz, so a table sized for them holds the row):
+ * num_counts equals sym_counts.  Bin b >= 1 holds rows with key in
+ * (8*2^(b-1), 8*2^b] (bin 1: 1..16), bin 0 empty rows, bin 12 the rows
+ * beyond every LDS table of the pass in question.
  * SPG_ERR_ARG if the counts were not read back (capture-safe call). */
 int spgemm_plan_bins(spg_plan plan, int32_t *sym_counts, int32_t *num_counts);
 

@@ -232,7 +232,7 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
     }
   }
   // a1 + a2: products per row and bins by products
-  e = launch_binning(dpr, nullptr, 0, m, D.sym_maxbin, L, ws, C_row_ptr, st);
+  e = launch_binning(dpr, m, D.sym_maxbin, L, ws, C_row_ptr, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
   BinPlan sbp;
   if (eager) {
@@ -250,9 +250,9 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
   if (e != hipSuccess) return SPG_ERR_HIP;
   e = launch_scan(C_row_ptr, m, eager ? -1 : capacity, L, ws, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
-  // numeric bins by exact row nnz
-  e = launch_binning(dpr, C_row_ptr, 1, m, D.num_maxbin_f32, L, ws, nullptr, st);
-  if (e != hipSuccess) return SPG_ERR_HIP;
+  // The numeric pass keeps the bins by products: a row's products bound its
+  // distinct columns, so every numeric table or staging area sized by them
+  // holds the row, and no second binning pass is needed.
   if (eager) {
     int rc = read_header(p, st);
     if (rc) return rc;
@@ -260,7 +260,7 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
     if (rc) return rc;
     p->nnz = p->host_hdr->nnz_total;
     p->products = p->host_hdr->products_total;
-    for (int b = 0; b < kNB; ++b) p->num_count[b] = p->host_hdr->bin_count[b];
+    for (int b = 0; b < kNB; ++b) p->num_count[b] = p->sym_count[b];
     p->counts_known = true;
     *C_nnz_host = p->nnz;
   }
@@ -579,7 +579,7 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
       if (rc) return rc;
     }
   }
-  e = launch_binning(dpr, nullptr, 0, n, D.mcl_maxbin, L, ws, Y_row_ptr, st);
+  e = launch_binning(dpr, n, D.mcl_maxbin, L, ws, Y_row_ptr, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
   BinPlan bp;
   if (eager) {

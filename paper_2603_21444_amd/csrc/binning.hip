@@ -47,13 +47,12 @@ __global__ void k_validate(const int32_t *rp, const int32_t *col, int rows, int 
 }
 
 // ---------------------------------------------------------------------------
-// a1/a2: row key (products per row, or nnz of a C row) and bin id; per-block
-// bin histogram.  One thread per row, 256 rows per block.
+// a1/a2: row key (products per row) and bin id; per-block bin histogram and
+// the product total.  One thread per row, 256 rows per block.
 constexpr int kBinBlock = 256;
 
 __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict__ pr,
-                                                      const int32_t *__restrict__ crp,
-                                                      int mode, int maxbin, uint8_t *binid,
+                                                      int maxbin, uint8_t *binid,
                                                       int32_t *blockhist, int32_t *cnt_zero,
                                                       WsHeader *hdr) {
   __shared__ int hist[kNB];
@@ -66,84 +65,76 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   int64_t key = 0;
   bool longrow = false;
   if (i < m) {
-    if (mode == 0) {
-      const int K = pr->K;
-      int len = 0;
-      for (int k = 0; k < K; ++k) {
-        int as, ae;
-        a_row(pr->part[k], i, as, ae);
-        len += ae - as;
-      }
-      longrow = len > kWave;  // counted by the whole wave below
-      for (int k = 0; k < K && !longrow; ++k) {
-        const Part &P = pr->part[k];
-        int as, ae;
-        a_row(P, i, as, ae);
-        const SPG_GLOBAL int32_t *brp = gp(P.brp);
-        int p = as;
-        for (; p + 8 <= ae; p += 8) {  // eight independent gathers in flight
-          int r[8];
+    const int K = pr->K;
+    int len = 0;
+    for (int k = 0; k < K; ++k) {
+      int as, ae;
+      a_row(pr->part[k], i, as, ae);
+      len += ae - as;
+    }
+    longrow = len > kWave;  // counted by the whole wave below
+    for (int k = 0; k < K && !longrow; ++k) {
+      const Part &P = pr->part[k];
+      int as, ae;
+      a_row(P, i, as, ae);
+      const SPG_GLOBAL int32_t *brp = gp(P.brp);
+      int p = as;
+      for (; p + 8 <= ae; p += 8) {  // eight independent gathers in flight
+        int r[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) r[u] = a_entry_row(P, i, p + u);
+        for (int u = 0; u < 8; ++u) r[u] = a_entry_row(P, i, p + u);
 #pragma unroll
-          for (int u = 0; u < 8; ++u) key += brp[r[u] + 1] - brp[r[u]];
-        }
-        for (; p < ae; ++p) {
-          const int r = a_entry_row(P, i, p);
-          key += brp[r + 1] - brp[r];
-        }
+        for (int u = 0; u < 8; ++u) key += brp[r[u] + 1] - brp[r[u]];
       }
-    } else {
-      key = crp[i + 1] - crp[i];
+      for (; p < ae; ++p) {
+        const int r = a_entry_row(P, i, p);
+        key += brp[r + 1] - brp[r];
+      }
     }
   }
-  if (mode == 0) {
-    // rows with more than 64 entries: the wave sums their products together
-    uint64_t pend = __ballot(longrow);
-    while (pend) {
-      const int lead = __ffsll((unsigned long long)pend) - 1;
-      pend &= pend - 1;
-      const int ri = __shfl(i, lead);
-      int64_t part = 0;
-      for (int k = 0; k < pr->K; ++k) {
-        const Part &P = pr->part[k];
-        int as, ae;
-        a_row(P, ri, as, ae);
-        const SPG_GLOBAL int32_t *brp = gp(P.brp);
-        int p = as + lane_id();
-        for (; p + 3 * kWave < ae; p += 4 * kWave) {  // four gathers in flight per lane
-          int r[4];
+  // rows with more than 64 entries: the wave sums their products together
+  uint64_t pend = __ballot(longrow);
+  while (pend) {
+    const int lead = __ffsll((unsigned long long)pend) - 1;
+    pend &= pend - 1;
+    const int ri = __shfl(i, lead);
+    int64_t part = 0;
+    for (int k = 0; k < pr->K; ++k) {
+      const Part &P = pr->part[k];
+      int as, ae;
+      a_row(P, ri, as, ae);
+      const SPG_GLOBAL int32_t *brp = gp(P.brp);
+      int p = as + lane_id();
+      for (; p + 3 * kWave < ae; p += 4 * kWave) {  // four gathers in flight per lane
+        int r[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, ri, p + u * kWave);
+        for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, ri, p + u * kWave);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) part += brp[r[u] + 1] - brp[r[u]];
-        }
-        for (; p < ae; p += kWave) {
-          const int r = a_entry_row(P, ri, p);
-          part += brp[r + 1] - brp[r];
-        }
+        for (int u = 0; u < 4; ++u) part += brp[r[u] + 1] - brp[r[u]];
       }
-#pragma unroll
-      for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
-      if (lane_id() == lead) key = part;
+      for (; p < ae; p += kWave) {
+        const int r = a_entry_row(P, ri, p);
+        part += brp[r + 1] - brp[r];
+      }
     }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (lane_id() == lead) key = part;
   }
   if (i < m) {
-    if (mode == 0 && key == 0) cnt_zero[i] = 0;
+    if (key == 0) cnt_zero[i] = 0;
     int b = bin_of(key, maxbin);
     binid[i] = (uint8_t)b;
     atomicAdd(&hist[b], 1);
   }
-  if (mode == 0) {
-    // block sum of products -> header (int64)
-    long long v = key;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane_id() == 0) psum[threadIdx.x / kWave] = v;
-  }
+  // block sum of products -> header (int64)
+  long long v = key;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane_id() == 0) psum[threadIdx.x / kWave] = v;
   __syncthreads();
   // bin-major: blockhist[b * nblk + block]
   if (threadIdx.x < kNB) blockhist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = hist[threadIdx.x];
-  if (mode == 0 && threadIdx.x == 0) {
+  if (threadIdx.x == 0) {
     long long s = 0;
     for (int w = 0; w < kBinBlock / kWave; ++w) s += psum[w];
     atomicAdd((unsigned long long *)&hdr->products_total, (unsigned long long)s);
@@ -326,14 +317,14 @@ hipError_t launch_validate(const int32_t *rp, const int32_t *col, int rows, int 
   return hipGetLastError();
 }
 
-hipError_t launch_binning(const Problem *dpr, const int32_t *crp, int mode, int m, int maxbin,
-                          const WsLayout &L, char *ws, int32_t *cnt_zero, hipStream_t st) {
+hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const WsLayout &L, char *ws,
+                          int32_t *cnt_zero, hipStream_t st) {
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   const int nblk = m == 0 ? 1 : (m + kBinBlock - 1) / kBinBlock;
   uint8_t *binid = reinterpret_cast<uint8_t *>(ws + L.binid);
   int32_t *bh = reinterpret_cast<int32_t *>(ws + L.blockhist);
   int32_t *rows = reinterpret_cast<int32_t *>(ws + L.rows);
-  hipLaunchKernelGGL(k_rowkey, dim3(nblk), dim3(kBinBlock), 0, st, dpr, crp, mode, maxbin,
+  hipLaunchKernelGGL(k_rowkey, dim3(nblk), dim3(kBinBlock), 0, st, dpr, maxbin,
                      binid, bh, cnt_zero, hdr);
   hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, bh, nblk, hdr);
   hipLaunchKernelGGL(k_binscatter, dim3(nblk), dim3(kBinBlock), 0, st, binid, m, bh, rows, hdr);

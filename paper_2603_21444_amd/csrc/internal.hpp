@@ -60,8 +60,8 @@ hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool res
                         hipStream_t st);
 hipError_t launch_validate(const int32_t *rp, const int32_t *col, int rows, int ncols,
                            int64_t nnz, WsHeader *hdr, hipStream_t st);
-hipError_t launch_binning(const Problem *dpr, const int32_t *crp, int mode, int m, int maxbin,
-                          const WsLayout &L, char *ws, int32_t *cnt_zero, hipStream_t st);
+hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const WsLayout &L, char *ws,
+                          int32_t *cnt_zero, hipStream_t st);
 hipError_t launch_scan(int32_t *rp, int m, int64_t capacity, const WsLayout &L, char *ws,
                        hipStream_t st);
 hipError_t launch_symbolic_bins(const Problem *dpr, const BinPlan &bp, const WsLayout &L,
