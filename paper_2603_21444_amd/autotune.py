@@ -2,8 +2,9 @@
 
 For each bin that carries a noticeable share of the work it times the
 symbolic + numeric passes (HIP events, eager, outside any graph capture)
-over a few candidate (lanes per row, lanes per A entry) pairs and keeps the
-fastest; the other bins keep their current setting.  Results are cached in
+over a few candidate (lanes per row, lanes per A entry) pairs, then over the
+symbolic pass's own lanes per A entry, and keeps the fastest; the other bins
+keep their current setting.  Results are cached in
 a JSON file keyed by dtype, shape, number of block products and the
 rounded per-bin row histogram, so a capture reuses them without timing.
 """
@@ -32,6 +33,8 @@ CANDIDATES = {
     10: [(512, 16), (1024, 16)],
     11: [(1024, 16)],
 }
+# candidate lanes per A entry of the symbolic count
+SYM_SUB_CANDIDATES = (4, 8, 16)
 
 
 def default_cache_path() -> str:
@@ -88,6 +91,15 @@ def tune(As, Bs, reps: int = 3, cache_path: str | None = None, share: float = 0.
             if ms < best_ms:
                 best, best_ms = (lanes, sub), ms
         t.lanes[b], t.sub[b] = best
+        best_s = t.sym_sub[b]
+        for s in SYM_SUB_CANDIDATES:
+            if s == best_s:
+                continue
+            t.sym_sub[b] = s
+            ms = _time(As, Bs, t, reps)
+            if ms < best_ms:
+                best_s, best_ms = s, ms
+        t.sym_sub[b] = best_s
     if use_cache:
         cache[key] = _to_json(t)
         os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -97,8 +109,8 @@ def tune(As, Bs, reps: int = 3, cache_path: str | None = None, share: float = 0.
 
 
 def _to_json(t: binding.SpgTuning) -> dict:
-    return {"lanes": list(t.lanes), "sub": list(t.sub), "heavy_slots": t.heavy_slots,
-            "max_window": t.max_window}
+    return {"lanes": list(t.lanes), "sub": list(t.sub), "sym_sub": list(t.sym_sub),
+            "heavy_slots": t.heavy_slots, "max_window": t.max_window}
 
 
 def _from_json(d: dict) -> binding.SpgTuning:
@@ -107,6 +119,8 @@ def _from_json(d: dict) -> binding.SpgTuning:
         t.lanes[b] = v
     for b, v in enumerate(d["sub"]):
         t.sub[b] = v
+    for b, v in enumerate(d.get("sym_sub", [])):
+        t.sym_sub[b] = v
     t.heavy_slots = d["heavy_slots"]
     t.max_window = d["max_window"]
     return t

@@ -45,6 +45,7 @@ class SpgCsr(C.Structure):
 
 class SpgTuning(C.Structure):
     _fields_ = [("lanes", C.c_int32 * SPG_NBINS), ("sub", C.c_int32 * SPG_NBINS),
+                ("sym_sub", C.c_int32 * SPG_NBINS),
                 ("heavy_slots", C.c_int32), ("max_window", C.c_int32)]
 
 

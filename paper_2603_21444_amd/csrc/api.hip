@@ -133,6 +133,9 @@ spg_tuning default_tuning() {
   for (int b = 0; b < kNB; ++b) {
     t.lanes[b] = lanes[b];
     t.sub[b] = 16;
+    // the count's one-wave kernel (bin 5) gains from more A entries in flight;
+    // block groups do not
+    t.sym_sub[b] = b == 5 ? 4 : 16;
   }
   t.heavy_slots = 0;
   t.max_window = kTail;
@@ -145,6 +148,7 @@ int check_tuning(const spg_tuning &t) {
   for (int b = 1; b < kNB; ++b) {
     if (!pow2(t.lanes[b]) || t.lanes[b] < 8 || t.lanes[b] > 1024) return SPG_ERR_ARG;
     if (!pow2(t.sub[b]) || t.sub[b] > 64) return SPG_ERR_ARG;
+    if (!pow2(t.sym_sub[b]) || t.sym_sub[b] > 64) return SPG_ERR_ARG;
   }
   if (t.heavy_slots < 0 || t.max_window < 1 || t.max_window > kTail) return SPG_ERR_ARG;
   return SPG_OK;
@@ -173,14 +177,15 @@ int status_from_bits(int bits) {
   return SPG_OK;
 }
 
-BinPlan make_binplan(spg_plan p, int maxbin, bool counts_known, const int *counts) {
+BinPlan make_binplan(spg_plan p, int maxbin, bool counts_known, const int *counts,
+                     bool symbolic = false) {
   BinPlan bp;
   bp.known = counts_known;
   if (counts_known)
     for (int b = 0; b < kNB; ++b) bp.count[b] = counts[b];
   for (int b = 0; b < kNB; ++b) {
     bp.lanes[b] = p->tun.lanes[b];
-    bp.sub[b] = p->tun.sub[b];
+    bp.sub[b] = symbolic ? p->tun.sym_sub[b] : p->tun.sub[b];
   }
   bp.maxbin = maxbin;
   bp.heavy_slots = p->L.heavy_slots;
@@ -240,10 +245,10 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
     if (rc) return rc;
     rc = status_from_bits(p->host_hdr->status);
     if (rc) return rc;
-    sbp = make_binplan(p, D.sym_maxbin, true, p->host_hdr->bin_count);
+    sbp = make_binplan(p, D.sym_maxbin, true, p->host_hdr->bin_count, true);
     for (int b = 0; b < kNB; ++b) p->sym_count[b] = p->host_hdr->bin_count[b];
   } else {
-    sbp = make_binplan(p, D.sym_maxbin, false, nullptr);
+    sbp = make_binplan(p, D.sym_maxbin, false, nullptr, true);
   }
   // a3: exact row counts, then the scan into row_ptr
   e = launch_symbolic_bins(dpr, sbp, L, ws, C_row_ptr, st);

@@ -13,9 +13,19 @@ def test_every_candidate_is_accepted_by_the_library():
     p = binding.Plan()
     for b, cands in autotune.CANDIDATES.items():
         for lanes, sub in cands:
-            t = binding.default_tuning()
-            t.lanes[b], t.sub[b] = lanes, sub
-            p.set_tuning(t)  # raises SpgError when rejected
+            for s in autotune.SYM_SUB_CANDIDATES:
+                t = binding.default_tuning()
+                t.lanes[b], t.sub[b], t.sym_sub[b] = lanes, sub, s
+                p.set_tuning(t)  # raises SpgError when rejected
+
+
+def test_library_rejects_bad_symbolic_sub():
+    p = binding.Plan()
+    for bad in (0, 3, 128):
+        t = binding.default_tuning()
+        t.sym_sub[4] = bad
+        with pytest.raises(binding.SpgError):
+            p.set_tuning(t)
 
 
 def test_candidates_cover_the_default():
@@ -23,16 +33,18 @@ def test_candidates_cover_the_default():
     t = binding.default_tuning()
     for b, cands in autotune.CANDIDATES.items():
         assert (t.lanes[b], min(t.sub[b], t.lanes[b])) in cands, b
+        assert t.sym_sub[b] in autotune.SYM_SUB_CANDIDATES, b
 
 
 def test_json_round_trip():
     t = binding.default_tuning()
-    t.lanes[5], t.sub[5] = 32, 8
+    t.lanes[5], t.sub[5], t.sym_sub[5] = 32, 8, 16
     t.heavy_slots = 7
     d = json.loads(json.dumps(autotune._to_json(t)))
     u = autotune._from_json(d)
     assert list(u.lanes) == list(t.lanes)
     assert list(u.sub) == list(t.sub)
+    assert list(u.sym_sub) == list(t.sym_sub)
     assert u.heavy_slots == 7 and u.max_window == t.max_window
 
 
@@ -62,6 +74,7 @@ def test_tuned_plan_matches_default(tmp_path):
     assert (tmp_path / "t.json").exists()
     t2 = autotune.tune([dA], [dB], reps=1, cache_path=str(tmp_path / "t.json"))
     assert list(t2.lanes) == list(t.lanes) and list(t2.sub) == list(t.sub)
+    assert list(t2.sym_sub) == list(t.sym_sub)
     plan = binding.Plan(tuning=t)
     rp, nnz = plan.symbolic([dA], [dB])
     col, vals = plan.numeric([dA], [dB], rp, nnz)
@@ -69,3 +82,39 @@ def test_tuned_plan_matches_default(tmp_path):
     got = binding.DeviceCSR((3000, 5000), rp, col, vals).to_host()
     ref, S = oracle.spgemm(A, B, with_abs=True)
     assert_same_csr(got, ref, S, np.float64, what="tuned plan")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_every_candidate_gives_the_oracle_product(dtype):
+    """Every bin under each of its candidates (and the extreme lanes-per-entry
+    settings 1 and 64, in both passes) gives the oracle's product on rows
+    spanning all LDS bins."""
+    import torch
+    from paper_2603_21444_amd import synth
+    import oracle
+    from helpers import assert_same_csr
+    A = synth.varnnz_csr(3000, 4000, 0, 200, 9, dtype, "normal", stream=0)
+    B = synth.varnnz_csr(4000, 30000, 0, 64, 9, dtype, "normal", stream=1)
+    dA, dB = binding.to_device(A), binding.to_device(B)
+    ref, S = oracle.spgemm(A.with_data(A.data.astype(np.float64)),
+                           B.with_data(B.data.astype(np.float64)), with_abs=True)
+    settings = []
+    for i in range(4):
+        t = binding.default_tuning()
+        for b, cands in autotune.CANDIDATES.items():
+            t.lanes[b], t.sub[b] = cands[i % len(cands)]
+            t.sym_sub[b] = autotune.SYM_SUB_CANDIDATES[i % len(autotune.SYM_SUB_CANDIDATES)]
+        settings.append((f"candidate {i}", t))
+    for sub, ssub in ((1, 64), (64, 1)):
+        t = binding.default_tuning()
+        for b in range(1, 12):
+            t.sub[b], t.sym_sub[b] = sub, ssub
+        settings.append((f"sub {sub} sym_sub {ssub}", t))
+    for what, t in settings:
+        plan = binding.Plan(tuning=t)
+        rp, nnz = plan.symbolic([dA], [dB])
+        col, vals = plan.numeric([dA], [dB], rp, nnz)
+        torch.cuda.synchronize()
+        got = binding.DeviceCSR(A.shape[:1] + B.shape[1:], rp, col, vals).to_host()
+        assert_same_csr(got, ref, S, dtype, what=what)
