@@ -48,8 +48,18 @@ __global__ void k_validate(const int32_t *rp, const int32_t *col, int rows, int 
 
 // ---------------------------------------------------------------------------
 // a1/a2: row key (products per row) and bin id; per-block bin histogram and
-// the product total.  One thread per row, 256 rows per block.
+// the product total.  One thread per row, 256 rows per block.  A thread
+// reads its row's A columns four at a time (16-byte loads) and the bounds of
+// each selected B row with one 8-byte load: the rows of a wave's lanes lie
+// far apart, so every load instruction touches up to 64 cache lines and the
+// number of instructions is what costs.
 constexpr int kBinBlock = 256;
+
+__device__ __forceinline__ int brow_len(const SPG_GLOBAL int32_t *brp, int r) {
+  int2 b;
+  __builtin_memcpy(&b, brp + r, sizeof(b));  // brp[r], brp[r + 1] in one load
+  return b.y - b.x;
+}
 
 __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict__ pr,
                                                       int maxbin, uint8_t *binid,
@@ -78,18 +88,20 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
       int as, ae;
       a_row(P, i, as, ae);
       const SPG_GLOBAL int32_t *brp = gp(P.brp);
+      if (P.a_identity) {  // A = I: the row's products are B row i
+        key += brow_len(brp, i);
+        continue;
+      }
+      const SPG_GLOBAL int32_t *acol = gp(P.acol);
       int p = as;
-      for (; p + 8 <= ae; p += 8) {  // eight independent gathers in flight
+      for (; p + 8 <= ae; p += 8) {  // eight entries, eight gathers in flight
         int r[8];
+        __builtin_memcpy(&r[0], acol + p, 4 * sizeof(int));
+        __builtin_memcpy(&r[4], acol + p + 4, 4 * sizeof(int));
 #pragma unroll
-        for (int u = 0; u < 8; ++u) r[u] = a_entry_row(P, i, p + u);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) key += brp[r[u] + 1] - brp[r[u]];
+        for (int u = 0; u < 8; ++u) key += brow_len(brp, r[u]);
       }
-      for (; p < ae; ++p) {
-        const int r = a_entry_row(P, i, p);
-        key += brp[r + 1] - brp[r];
-      }
+      for (; p < ae; ++p) key += brow_len(brp, acol[p]);
     }
   }
   // rows with more than 64 entries: the wave sums their products together
@@ -110,12 +122,9 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
 #pragma unroll
         for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, ri, p + u * kWave);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) part += brp[r[u] + 1] - brp[r[u]];
+        for (int u = 0; u < 4; ++u) part += brow_len(brp, r[u]);
       }
-      for (; p < ae; p += kWave) {
-        const int r = a_entry_row(P, ri, p);
-        part += brp[r + 1] - brp[r];
-      }
+      for (; p < ae; p += kWave) part += brow_len(brp, a_entry_row(P, ri, p));
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -141,67 +150,66 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   }
 }
 
-// Exclusive scan of the per-block histograms in bin-major order (one block
-// of 1024 threads): wave b owns bin b, whose block counts are contiguous.
-// The wave reads them in coalesced chunks of 64, eight chunks in flight per
-// lane: one pass for the bin total, a second one (after the totals of all
-// bins give the bin's base) writing each block's offset.
+// Exclusive scan of one bin's per-block counts (block b of kNB; the counts
+// of a bin are contiguous), in place and relative to the bin's start; the
+// bin's total goes to the header.  Each thread takes four consecutive
+// counts of a 4096-count chunk: one load round trip and one block scan per
+// chunk.
 __global__ __launch_bounds__(1024) void k_binscan(int32_t *blockhist, int nblk, WsHeader *hdr) {
-  constexpr int U = 8;
-  __shared__ int bintot[kNB];
-  const int b = threadIdx.x / kWave;  // 16 waves, one per bin
-  const int lane = lane_id();
+  __shared__ int wsum[1024 / kWave];
+  const int b = blockIdx.x, t = threadIdx.x, lane = lane_id(), w = t / kWave;
   int32_t *h = blockhist + (int64_t)b * nblk;
-  int tot = 0;
-  for (int c0 = 0; c0 < nblk; c0 += kWave * U) {
-    int v[U];
+  int carry = 0;
+  for (int c0 = 0; c0 < nblk; c0 += 4 * 1024) {
+    int v[4];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int idx = c0 + u * kWave + lane;
+    for (int u = 0; u < 4; ++u) {
+      const int idx = c0 + 4 * t + u;
       v[u] = idx < nblk ? h[idx] : 0;
     }
+    const int s = v[0] + v[1] + v[2] + v[3];
+    int x = s;
 #pragma unroll
-    for (int u = 0; u < U; ++u) tot += v[u];
-  }
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-  if (lane == 0) bintot[b] = tot;
-  __syncthreads();
-  int base = 0;
-  for (int bb = 0; bb < b; ++bb) base += bintot[bb];
-  int carry = base;
-  for (int c0 = 0; c0 < nblk; c0 += kWave * U) {
-    int v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int idx = c0 + u * kWave + lane;
-      v[u] = idx < nblk ? h[idx] : 0;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(x, off);
+      if (lane >= off) x += y;
     }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int x = v[u];
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-        const int y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-      }
-      const int idx = c0 + u * kWave + lane;
-      if (idx < nblk) h[idx] = carry + x - v[u];
-      carry += __shfl(x, kWave - 1);
+    for (int ww = 0; ww < 1024 / kWave; ++ww) {
+      const int c = wsum[ww];
+      pre += ww < w ? c : 0;
+      tot += c;
     }
+    __syncthreads();  // wsum is rewritten by the next chunk
+    int run = carry + pre + x - s;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = c0 + 4 * t + u;
+      if (idx < nblk) h[idx] = run;
+      run += v[u];
+    }
+    carry += tot;
   }
-  if (lane == 0) {
-    hdr->bin_count[b] = tot;
-    hdr->bin_start[b] = base;
-    if (b == kNB - 1) hdr->bin_start[kNB] = base + tot;
-  }
+  if (t == 0) hdr->bin_count[b] = carry;
 }
 
-// Stable scatter of row ids into the per-bin lists.
+// Stable scatter of row ids into the per-bin lists: bin start (prefix of
+// the bin totals) + the block's offset within the bin + rank in the block.
+// Block 0 publishes the bin starts.
 __global__ __launch_bounds__(kBinBlock) void k_binscatter(const uint8_t *binid, int m,
                                                           const int32_t *blockoff,
-                                                          int32_t *rows, const WsHeader *hdr) {
+                                                          int32_t *rows, WsHeader *hdr) {
   __shared__ int wcnt[kBinBlock / kWave][kNB];
+  __shared__ int binbase[kNB + 1];
+  if (threadIdx.x <= kNB) {
+    int s = 0;
+    for (int bb = 0; bb < (int)threadIdx.x; ++bb) s += hdr->bin_count[bb];
+    binbase[threadIdx.x] = s;
+    if (blockIdx.x == 0) hdr->bin_start[threadIdx.x] = s;
+  }
   if (hdr->status) return;
   const int i = blockIdx.x * kBinBlock + threadIdx.x;
   const int w = threadIdx.x / kWave;
@@ -214,7 +222,7 @@ __global__ __launch_bounds__(kBinBlock) void k_binscatter(const uint8_t *binid, 
   }
   __syncthreads();
   if (i < m) {
-    int off = blockoff[(int64_t)b * gridDim.x + blockIdx.x];
+    int off = binbase[b] + blockoff[(int64_t)b * gridDim.x + blockIdx.x];
     for (int ww = 0; ww < w; ++ww) off += wcnt[ww][b];
     rows[off + myrank] = i;
   }
@@ -326,7 +334,7 @@ hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const WsLayout 
   int32_t *rows = reinterpret_cast<int32_t *>(ws + L.rows);
   hipLaunchKernelGGL(k_rowkey, dim3(nblk), dim3(kBinBlock), 0, st, dpr, maxbin,
                      binid, bh, cnt_zero, hdr);
-  hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, bh, nblk, hdr);
+  hipLaunchKernelGGL(k_binscan, dim3(kNB), dim3(1024), 0, st, bh, nblk, hdr);
   hipLaunchKernelGGL(k_binscatter, dim3(nblk), dim3(kBinBlock), 0, st, binid, m, bh, rows, hdr);
   return hipGetLastError();
 }
