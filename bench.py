@@ -333,7 +333,7 @@ def main():
             "rows": n, "nnz_per_row": d, "products": products, "nnz_C": r["nnz"], "seed": SEED + 1,
         },
         "roofline": {
-            "kernel": "numeric pass (row-binned LDS-hash kernels, all bins of one step)",
+            "kernel": "numeric pass (row-binned LDS kernels: bucket placement, hash, sort fallback; all bins of one step)",
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
