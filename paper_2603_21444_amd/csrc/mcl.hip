@@ -297,7 +297,10 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
 constexpr int kPanel = 16384;  // columns per panel: 128 KiB of int64 in LDS
 constexpr int kPT = 1024;      // threads of a heavy block
 constexpr int kCPT = kPanel / kPT;  // panel columns per thread in the epilogue
-constexpr int kPU = 4;        // entry groups a wave serves at once
+#ifndef SPG_MCL_PU
+#define SPG_MCL_PU 4
+#endif
+constexpr int kPU = SPG_MCL_PU;  // entry groups a wave serves at once
 constexpr int kPE = 1024;     // entries whose cursors stay in LDS
 static_assert(kCPT == 16, "the epilogue reads one 16-bit half of a bitmap word per thread");
 
@@ -374,13 +377,17 @@ __device__ __forceinline__ int panel_accumulate(const SPG_GLOBAL int32_t *bcol,
     int c[kPU], en[kPU];
     float a[kPU];
     bool act[kPU];
+    // Every read below uses an in-range index for every lane (entry 0; B
+    // element 0, which exists since a heavy row has products), so the reads
+    // of all kPU groups are issued before the first wait.
 #pragma unroll
     for (int u = 0; u < kPU; ++u) {
       const int e = e0 + u * EPW + sub;
       act[u] = e < nA;
-      c[u] = act[u] ? (int)ecur[e] : 0;
-      en[u] = act[u] ? (int)eend[e] : 0;
-      a[u] = act[u] ? eval[e] : 0.f;
+      const int es = act[u] ? e : 0;
+      c[u] = (int)ecur[es];
+      en[u] = (int)eend[es];
+      a[u] = eval[es];
     }
     bool more = true;
     while (more) {
@@ -390,8 +397,10 @@ __device__ __forceinline__ int panel_accumulate(const SPG_GLOBAL int32_t *bcol,
       for (int u = 0; u < kPU; ++u) {
         const int idx = c[u] + q;
         const bool ld = act[u] && idx < en[u];
-        col[u] = ld ? bcol[idx] : INT32_MAX;
-        v[u] = ld ? bval[idx] : 0.f;
+        const int li = ld ? idx : 0;
+        col[u] = bcol[li];
+        v[u] = bval[li];
+        col[u] = ld ? col[u] : INT32_MAX;
       }
       more = false;
 #pragma unroll
@@ -405,13 +414,13 @@ __device__ __forceinline__ int panel_accumulate(const SPG_GLOBAL int32_t *bcol,
         }
         const uint64_t m = __ballot(in);
         const int k = __popcll((m >> base) & (S == kWave ? ~0ull : ((1ull << S) - 1)));
-        const int nxt = __shfl(col[u], base + (k < S ? k : 0));
+        // the group's lane k holds the entry's first column past the panel
+        // (INT32_MAX once its row ended, or for an inactive group); the
+        // block-wide minimum comes later, so that lane keeps it
+        if (q == k) tmn = min(tmn, col[u]);
         if (act[u]) {
           c[u] += k;
-          if (k < S) {  // the entry left the panel (or its row ended)
-            act[u] = false;
-            tmn = min(tmn, nxt);
-          }
+          if (k < S) act[u] = false;  // the entry left the panel (or its row ended)
         }
         more = more || act[u];
       }
