@@ -801,6 +801,165 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
   }
 }
 
+// Numeric pass of heavy rows by column ranges.  The row's products are
+// counted per range of W = 2^log2W consecutive columns (LDS counters), a
+// block scan gives each range its segment of the slot's staging area, and a
+// second enumeration drops every product (column, value) into its range's
+// segment.  The ranges are then taken in column order: a range's products
+// are added into an LDS panel of W values (a presence bitmap marks the
+// columns) and the panel is walked in column order, so the output row comes
+// out sorted, with one block scan per non-empty range.  Every atomic stays
+// in LDS; the dense global accumulator of k_num_heavy spread the adds of
+// all blocks over one accumulator of n values each, far more than L2 holds.
+// A row with more products than the staging area holds takes that dense
+// path (the slot's memory as accumulator, the panel as bitmap when n fits).
+constexpr int kRngMax = 1024;  // column ranges a row may span
+
+template <typename VT>
+__device__ void heavy_dense_row(const Problem *__restrict__ pr, int i, int lS, Stage<VT> st,
+                                uint32_t *map, VT *acc, int n, int *wtot, int rs, int re,
+                                int32_t *__restrict__ ccol, VT *__restrict__ cval,
+                                WsHeader *__restrict__ hdr) {
+  const int tid = threadIdx.x;
+  const int nw = (n + 31) >> 5;
+  for (int w = tid; w < nw; w += 1024) map[w] = 0u;
+  for (int c = tid; c < n; c += 1024) acc[c] = VT(0);
+  __threadfence();
+  __syncthreads();
+  auto fadd = each_product([&](int col, VT v) {
+    const uint32_t bit = 1u << (col & 31);
+    if (!(map[col >> 5] & bit)) atomicOr(&map[col >> 5], bit);
+    global_add(&acc[col], v);
+  });
+  for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fadd);
+  __threadfence();
+  __syncthreads();
+  int pre = 0;
+  for (int w0 = 0; w0 < nw; w0 += 1024) {
+    const int wb = w0 + tid;
+    uint32_t wd = wb < nw ? map[wb] : 0u;
+    int tot;
+    int o = rs + pre + group_excl_scan<true, 1024>(__popc(wd), tid, wtot, tot);
+    if (wb < nw) map[wb] = 0u;  // leaves the bitmap (possibly the LDS panel) clear
+    while (wd) {
+      const int col = (wb << 5) + __ffs(wd) - 1;
+      wd &= wd - 1;
+      if (o < re) {
+        ccol[o] = col;
+        cval[o] = acc[col];
+      }
+      ++o;
+    }
+    pre += tot;
+  }
+  if (tid == 0 && pre != re - rs) atomicOr(&hdr->status, kStatInvalid);
+  __syncthreads();
+}
+
+template <typename VT>
+__global__ __launch_bounds__(1024) void k_num_heavy_rng(
+    const Problem *__restrict__ pr, const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
+    int blo, int lS, int log2W, uint32_t *gbitmap, char *slots, size_t slot_bytes,
+    const int32_t *__restrict__ crp, int32_t *__restrict__ ccol, VT *__restrict__ cval) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int W = 1 << log2W;
+  VT *panel = reinterpret_cast<VT *>(smem_raw);                 // W values
+  uint32_t *pmap = reinterpret_cast<uint32_t *>(panel + W);     // W / 32 words
+  __shared__ int rstart[kRngMax + 1];  // range segment starts (exclusive scan of the counts)
+  __shared__ int rpos[kRngMax];        // counts, then the next free position of each segment
+  __shared__ int wtot[16];
+  __shared__ int sb[1024], sl[1024];
+  __shared__ VT sa[1024];
+  if (hdr->status) return;
+  const int n = pr->n;
+  const int start = hdr->bin_start[blo];
+  const int count = hdr->bin_start[kHeavyBin + 1] - start;
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= count) return;
+  char *slot = slots + (size_t)blockIdx.x * slot_bytes;
+  const size_t capz = slot_bytes / (4 + sizeof(VT)) & ~(size_t)1;  // even: values 8-byte aligned
+  const int cap = capz < (size_t)INT32_MAX ? (int)capz : INT32_MAX - 1;
+  int32_t *scol = reinterpret_cast<int32_t *>(slot);
+  VT *sval = reinterpret_cast<VT *>(slot + (size_t)cap * 4);
+  const int R = (int)(((int64_t)n + W - 1) >> log2W);  // <= kRngMax (launcher)
+  const int nwords = W >> 5;
+  Stage<VT> st{sb, sl, sa};
+  for (int c = tid; c < W; c += 1024) panel[c] = VT(0);
+  for (int w = tid; w < nwords; w += 1024) pmap[w] = 0u;
+  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+    const int i = rows[start + ri];
+    const int rs = crp[i], re = crp[i + 1];
+    // 1. products per range
+    for (int r = tid; r < R; r += 1024) rpos[r] = 0;
+    __syncthreads();
+    auto fcount = each_product([&](int col, VT) { atomicAdd(&rpos[col >> log2W], 1); });
+    for_each_product<true, false, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fcount);
+    __syncthreads();
+    // 2. segment starts (R <= 1024: one range per thread)
+    int P;
+    {
+      const int c = tid < R ? rpos[tid] : 0;
+      int tot;
+      const int off = group_excl_scan<true, 1024>(c, tid, wtot, tot);
+      if (tid < R) {
+        rstart[tid] = off;
+        rpos[tid] = off;
+      }
+      if (tid == 0) rstart[R] = tot;
+      P = tot;
+      __syncthreads();
+    }
+    if (P > cap) {  // more products than the staging area holds
+      uint32_t *map = n <= W * (int)sizeof(VT) * 8 ? reinterpret_cast<uint32_t *>(panel)
+                                                   : gbitmap + (size_t)blockIdx.x * ((n + 31) >> 5);
+      heavy_dense_row<VT>(pr, i, lS, st, map, reinterpret_cast<VT *>(slot), n, wtot, rs, re, ccol,
+                          cval, hdr);
+      continue;
+    }
+    // 3. every product into its range's segment
+    auto fput = each_product([&](int col, VT v) {
+      const int p = atomicAdd(&rpos[col >> log2W], 1);
+      scol[p] = col;
+      sval[p] = v;
+    });
+    for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fput);
+    __threadfence();  // the staged pairs are read back by other threads of the block
+    __syncthreads();
+    // 4. the ranges in column order
+    int o = rs;
+    for (int r = 0; r < R; ++r) {
+      const int s0 = rstart[r], s1 = rstart[r + 1];
+      if (s0 == s1) continue;  // same value in every thread
+      const int base = r << log2W;
+      for (int p = s0 + tid; p < s1; p += 1024) {
+        const int cl = scol[p] - base;
+        lds_add(&panel[cl], sval[p]);
+        atomicOr(&pmap[cl >> 5], 1u << (cl & 31));
+      }
+      __syncthreads();
+      uint32_t wd = tid < nwords ? pmap[tid] : 0u;
+      int tot;
+      int off = o + group_excl_scan<true, 1024>(__popc(wd), tid, wtot, tot);
+      if (tid < nwords) pmap[tid] = 0u;
+      while (wd) {
+        const int cl = (tid << 5) + __ffs(wd) - 1;
+        wd &= wd - 1;
+        const VT v = panel[cl];
+        panel[cl] = VT(0);
+        if (off < re) {  // the symbolic count bounds the row (a changed pattern is flagged)
+          ccol[off] = base + cl;
+          cval[off] = v;
+        }
+        ++off;
+      }
+      o += tot;
+      __syncthreads();
+    }
+    if (tid == 0 && o != re) atomicOr(&hdr->status, kStatInvalid);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 
@@ -817,6 +976,17 @@ static int log2i(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
   return l;
+}
+
+// Bytes of one heavy slot in the workspace's heavy region.
+static size_t heavy_slot_bytes(int n) { return ((size_t)(n > 1 ? n : 1) + 4) * 8; }
+
+// Static LDS of k_num_heavy_rng (range starts and cursors, scan partials,
+// staged entries).
+template <typename VT>
+static size_t heavy_rng_static_lds() {
+  return (size_t)(kRngMax + 1) * 4 + (size_t)kRngMax * 4 + 16 * 4 + (size_t)1024 * (8 + sizeof(VT)) +
+         256;  // alignment padding
 }
 
 // A heavy row's column bitmap lives in LDS when it fits one block.
@@ -1019,7 +1189,14 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
     const int grid = grid_for(hc, 1, bp.heavy_slots);
     VT *acc = reinterpret_cast<VT *>(ws + L.heavyacc);
     const int lS = sub_log2(bp, kHeavyBin, 1024);
-    if (lds_bitmap_fits(bp.n, 8 * 1024 + 1024 * sizeof(VT))) {
+    const int log2W = sizeof(VT) == 4 ? 15 : 14;  // a 128 KiB panel
+    const size_t rlds = ((size_t)sizeof(VT) << log2W) + ((size_t)4 << (log2W - 5));
+    if ((int64_t)bp.n <= ((int64_t)kRngMax << log2W) &&
+        rlds + heavy_rng_static_lds<VT>() <= D.lds_per_block) {
+      hipLaunchKernelGGL((k_num_heavy_rng<VT>), dim3(grid), dim3(1024), rlds, st, dpr, rows, hdr,
+                         bp.maxbin + 1, lS, log2W, reinterpret_cast<uint32_t *>(ws + L.heavymap),
+                         ws + L.heavyacc, heavy_slot_bytes(bp.n), crp, ccol, cval);
+    } else if (lds_bitmap_fits(bp.n, 8 * 1024 + 1024 * sizeof(VT))) {
       const size_t lds = (size_t)((bp.n + 31) >> 5) * 4;
       hipLaunchKernelGGL((k_num_heavy<true, VT>), dim3(grid), dim3(1024), lds, st, dpr, rows,
                          hdr, bp.maxbin + 1, lS, (uint32_t *)nullptr, acc, crp, ccol, cval);
@@ -1074,6 +1251,8 @@ hipError_t configure_lds_limits(size_t lds_max) {
       reinterpret_cast<const void *>(&k_num_fallback<double>),
       reinterpret_cast<const void *>(&k_num_heavy<true, float>),
       reinterpret_cast<const void *>(&k_num_heavy<true, double>),
+      reinterpret_cast<const void *>(&k_num_heavy_rng<float>),
+      reinterpret_cast<const void *>(&k_num_heavy_rng<double>),
   };
   num_kernels<float, true>(ks);
   num_kernels<float, false>(ks);

@@ -82,6 +82,21 @@ def test_heavy_rows_global_bitmap(B):
     check(B, A, Bm, np.float32, what="heavy, wide")
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_heavy_rows_beyond_the_staging_area(B, dtype):
+    """Heavy rows with more products than the output has columns (+4): the
+    column-range kernel cannot stage them and adds them densely instead;
+    the other heavy rows of the same launch take the range path."""
+    n = 40000
+    A = synth.varnnz_csr(200, 4000, 1, 20, 13, dtype, "normal", stream=0)
+    dense_rows = synth.uniform_csr(3, 4000, 3000, 13, dtype, "normal", stream=2)
+    A = _replace_rows(A, [7, 100, 199], dense_rows)  # ~60000 products > n + 4: dense
+    mid_rows = synth.uniform_csr(2, 4000, 1000, 14, dtype, "normal", stream=3)
+    A = _replace_rows(A, [50, 51], mid_rows)  # ~20000 products: heavy, staged by range
+    Bm = synth.varnnz_csr(4000, n, 10, 30, 13, dtype, "normal", stream=1)
+    check(B, A, Bm, dtype, what="heavy beyond staging")
+
+
 def _replace_rows(A, rows, R):
     """A with rows `rows` replaced by the rows of R (same column count)."""
     rows = list(rows)
