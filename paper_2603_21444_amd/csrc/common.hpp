@@ -108,6 +108,18 @@ __device__ inline void lds_add(T *p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// LDS float add by compare-and-swap: on this chip cheaper than the LDS
+// float atomic when lanes rarely hit the same word.  FP64 keeps the atomic.
+__device__ __forceinline__ void lds_add_cas(float *p, float v) {
+  uint32_t *u = reinterpret_cast<uint32_t *>(p);
+  uint32_t old = *u, seen;
+  do {
+    seen = old;
+    old = atomicCAS(u, seen, __float_as_uint(__uint_as_float(seen) + v));
+  } while (old != seen);
+}
+__device__ __forceinline__ void lds_add_cas(double *p, double v) { lds_add(p, v); }
+
 template <typename T>
 __device__ inline void global_add(T *p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

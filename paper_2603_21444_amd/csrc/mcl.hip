@@ -82,11 +82,11 @@ struct MclInsert {
       group_sync<false>();
 #pragma unroll
       for (int u = 0; u < N; ++u)
-        if (ok[u] && old[u] != kEmpty) lds_add(&val[h[u]], v[u]);
+        if (ok[u] && old[u] != kEmpty) lds_add_cas(&val[h[u]], v[u]);
     } else {
 #pragma unroll
       for (int u = 0; u < N; ++u)
-        if (ok[u]) lds_add(&val[h[u]], v[u]);
+        if (ok[u]) lds_add_cas(&val[h[u]], v[u]);
     }
   }
 };

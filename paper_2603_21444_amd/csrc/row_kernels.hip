@@ -815,18 +815,6 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
 // path (the slot's memory as accumulator, the panel as bitmap when n fits).
 constexpr int kRngMax = 1024;  // column ranges a row may span
 
-// LDS float add by compare-and-swap (cheaper on this chip than the LDS
-// float atomic when lanes rarely hit the same word); FP64 keeps the atomic.
-__device__ __forceinline__ void lds_add_cas(float *p, float v) {
-  uint32_t *u = reinterpret_cast<uint32_t *>(p);
-  uint32_t old = *u, seen;
-  do {
-    seen = old;
-    old = atomicCAS(u, seen, __float_as_uint(__uint_as_float(seen) + v));
-  } while (old != seen);
-}
-__device__ __forceinline__ void lds_add_cas(double *p, double v) { lds_add(p, v); }
-
 template <typename VT>
 __device__ void heavy_dense_row(const Problem *__restrict__ pr, int i, int lS, Stage<VT> st,
                                 uint32_t *map, VT *acc, int n, int *wtot, int rs, int re,
