@@ -226,8 +226,10 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
     // every later kernel exits once the status word is raised, so invalid
     // operands are never dereferenced; eagerly the call returns right here
     for (int k = 0; k < pr.K; ++k) {
-      if (A) launch_validate(A[k].row_ptr, A[k].col_idx, A[k].nrows, A[k].ncols, A[k].nnz, hdr, st);
-      launch_validate(B[k].row_ptr, B[k].col_idx, B[k].nrows, B[k].ncols, B[k].nnz, hdr, st);
+      if (A) e = launch_validate(A[k].row_ptr, A[k].col_idx, A[k].nrows, A[k].ncols, A[k].nnz, hdr, st);
+      if (e != hipSuccess) return SPG_ERR_HIP;
+      e = launch_validate(B[k].row_ptr, B[k].col_idx, B[k].nrows, B[k].ncols, B[k].nnz, hdr, st);
+      if (e != hipSuccess) return SPG_ERR_HIP;
     }
     if (eager) {
       int rc = read_header(p, st);
@@ -576,7 +578,8 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
   if (e != hipSuccess) return SPG_ERR_HIP;
   const bool eager = Y_nnz_host != nullptr;
   if (plan->flags & SPG_FLAG_VALIDATE) {
-    launch_validate(X->row_ptr, X->col_idx, n, n, X->nnz, hdr, st);
+    e = launch_validate(X->row_ptr, X->col_idx, n, n, X->nnz, hdr, st);
+    if (e != hipSuccess) return SPG_ERR_HIP;
     if (eager) {
       rc = read_header(plan, st);
       if (rc) return rc;
