@@ -29,12 +29,12 @@ CANDIDATES = {
     6: [(64, 16), (64, 32), (128, 16)],
     7: [(64, 16), (128, 16), (256, 16)],
     8: [(128, 16), (256, 16), (256, 32)],
-    9: [(256, 16), (512, 16)],
+    9: [(512, 32), (512, 16), (256, 16)],
     10: [(512, 16), (1024, 16)],
     11: [(1024, 16)],
 }
 # candidate lanes per A entry of the symbolic count
-SYM_SUB_CANDIDATES = (4, 8, 16)
+SYM_SUB_CANDIDATES = (4, 8, 16, 32)
 
 
 def default_cache_path() -> str:

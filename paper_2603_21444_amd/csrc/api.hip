@@ -132,10 +132,11 @@ spg_tuning default_tuning() {
   const int lanes[kNB] = {0, 8, 16, 16, 32, 64, 128, 256, 256, 512, 1024, 1024, 1024, 1024, 1024, 1024};
   for (int b = 0; b < kNB; ++b) {
     t.lanes[b] = lanes[b];
-    t.sub[b] = 16;
-    // the count's one-wave kernel (bin 5) gains from more A entries in flight;
-    // block groups do not
-    t.sym_sub[b] = b == 5 ? 4 : 16;
+    // lanes per A entry: 16, but 32 for bin 9 (rows of 2049..4096 products,
+    // 512-lane groups), and 4 for the count's one-wave kernel (bin 5), which
+    // gains from more A entries in flight
+    t.sub[b] = b == 9 ? 32 : 16;
+    t.sym_sub[b] = b == 5 ? 4 : b == 9 ? 32 : 16;
   }
   t.heavy_slots = 0;
   t.max_window = kTail;
