@@ -659,7 +659,11 @@ size_t bucket_lds_bytes(int b, size_t vbytes) {
 
 // ---------------------------------------------------------------------------
 
-size_t sym_wave_lds_bytes(int b) { return (size_t)4 * bin_slots(b) * 4 + (size_t)8 * kWave * 4; }
+// Slots of the count's table per row: four times the bin's upper edge (load
+// <= 1/4, fewer probe round trips per insert).  Four waves' tables still fit
+// eight blocks per CU; eight times the edge would halve the resident waves.
+static int sym_wave_slots(int b) { return 2 * bin_slots(b); }
+size_t sym_wave_lds_bytes(int b) { return (size_t)4 * sym_wave_slots(b) * 4 + (size_t)8 * kWave * 4; }
 
 int num_wave_slots(int b) {
   const int need = bin_slots(b) + kTail;
@@ -690,7 +694,7 @@ void launch_sym_wave(const Problem *dpr, const int32_t *rows, const WsHeader *hd
                      int lS, int count, int32_t *cnt, hipStream_t st) {
   const size_t lds = sym_wave_lds_bytes(bin);
   int lt = 0;
-  while ((1 << lt) < bin_slots(bin)) ++lt;
+  while ((1 << lt) < sym_wave_slots(bin)) ++lt;
   hipLaunchKernelGGL(k_sym_wave, dim3(wave_grid(count, lds, 4 * SPG_WAVE_WAVES)), dim3(256), lds, st,
                      dpr, rows, hdr, bin, lS, lt, cnt);
 }
