@@ -588,7 +588,11 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
       if (rc) return rc;
     }
   }
-  e = launch_binning(dpr, n, D.mcl_maxbin, L, ws, Y_row_ptr, st);
+  // one bin past the largest LDS table: MCL rows repeat columns a lot, so
+  // most rows of that bin still fit the largest table; those whose probes
+  // overflow go to the panel kernel with the heavier bins
+  const int mcl_bins = D.mcl_maxbin + 1 < kHeavyBin ? D.mcl_maxbin + 1 : D.mcl_maxbin;
+  e = launch_binning(dpr, n, mcl_bins, L, ws, Y_row_ptr, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
   BinPlan bp;
   if (eager) {
@@ -596,9 +600,9 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
     if (rc) return rc;
     rc = status_from_bits(plan->host_hdr->status);
     if (rc) return rc;
-    bp = make_binplan(plan, D.mcl_maxbin, true, plan->host_hdr->bin_count);
+    bp = make_binplan(plan, mcl_bins, true, plan->host_hdr->bin_count);
   } else {
-    bp = make_binplan(plan, D.mcl_maxbin, false, nullptr);
+    bp = make_binplan(plan, mcl_bins, false, nullptr);
   }
   e = launch_mcl(dpr, bp, L, ws, r, prune, topk, cap, pcol, pval, Y_row_ptr, st);
   if (e != hipSuccess) return SPG_ERR_HIP;

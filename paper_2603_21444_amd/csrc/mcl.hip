@@ -731,14 +731,18 @@ hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, 
     if (bp.known && bp.count[b] == 0) continue;
     int G = bp.lanes[b];
     while (G < 1024 && mcl_lds_bytes(b, G) > D.lds_per_block) G *= 2;
+    // a bin past the largest table that fits takes that table (rows whose
+    // distinct columns overflow it are handed to the panel kernel)
+    int tb = b;
+    while (tb > 1 && mcl_lds_bytes(tb, G) > D.lds_per_block) --tb;
     const int WG = G <= kWave ? 256 : G;
     const int R = WG / G;
-    const size_t lds = mcl_lds_bytes(b, G);
+    const size_t lds = mcl_lds_bytes(tb, G);
     int cap_grid = D.cus * (int)std::max<size_t>(1, std::min<size_t>(D.lds_per_cu / lds, 2048 / WG));
     int grid = cap_grid;
     if (bp.known) grid = std::min(cap_grid, (bp.count[b] + R - 1) / R);
-    const int TT = num_table_slots(b, G);
-    const uint32_t mul = mono_mul(bin_slots(b), bp.n);
+    const int TT = num_table_slots(tb, G);
+    const uint32_t mul = mono_mul(bin_slots(tb), bp.n);
     int S = bp.sub[b] > 0 ? bp.sub[b] : 16;
     if (S > G) S = G;
     int lS = 0;
