@@ -274,7 +274,7 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
 // LDS kernel) is swept in panels of kPanel consecutive columns.  Every entry
 // a_ik of X row i keeps a cursor into B row k (sorted, as X is canonical).
 // In a panel, S lanes of a wave read S consecutive elements of one entry's B
-// row (coalesced), a wave serves kPU entries at once so that several loads
+// row (coalesced), a wave serves several entries at once so that several loads
 // are in flight, and a ballot over the S lanes tells how far the entry got
 // (elements are ascending, so those inside the panel are a prefix).  S is
 // chosen per row from the mean number of elements an entry has per panel.
@@ -297,10 +297,10 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
 constexpr int kPanel = 16384;  // columns per panel: 128 KiB of int64 in LDS
 constexpr int kPT = 1024;      // threads of a heavy block
 constexpr int kCPT = kPanel / kPT;  // panel columns per thread in the epilogue
-#ifndef SPG_MCL_PU
-#define SPG_MCL_PU 4
-#endif
-constexpr int kPU = SPG_MCL_PU;  // entry groups a wave serves at once
+// Entry groups a wave serves at once: six for rows whose entries have 32 or
+// more elements per panel (32 or 64 lanes per entry), four otherwise; more
+// groups spill past the 128 registers a 1024-thread block allows.
+constexpr int kPUDense = 6, kPUSparse = 4;
 constexpr int kPE = 1024;     // entries whose cursors stay in LDS
 static_assert(kCPT == 16, "the epilogue reads one 16-bit half of a bitmap word per thread");
 
@@ -362,7 +362,7 @@ __device__ __forceinline__ PanelRed panel_reduce(double s, int c, int mn, unsign
 
 // Adds the products of entries [0, nA) that fall in [plo, plo + width) and
 // advances their cursors; returns this lane's smallest next column.
-template <typename CurT>
+template <int kPU, typename CurT>
 __device__ __forceinline__ int panel_accumulate(const SPG_GLOBAL int32_t *bcol,
                                                 const SPG_GLOBAL float *bval, CurT *ecur,
                                                 const CurT *eend, const float *eval, int nA,
@@ -525,8 +525,11 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
     while (mnext < n) {
       const int plo = mnext & ~(kPanel - 1);
       const uint32_t width = plo < 0 ? 0u : (uint32_t)min(kPanel, n - plo);
-      const int tmn = panel_accumulate(bcol, bval, ccur, cend, cval, nA, lS, sigma, plo, width,
-                                       pacc, pbm);
+      const int tmn =
+          lS >= 5 ? panel_accumulate<kPUDense>(bcol, bval, ccur, cend, cval, nA, lS, sigma, plo,
+                                               width, pacc, pbm)
+                  : panel_accumulate<kPUSparse>(bcol, bval, ccur, cend, cval, nA, lS, sigma, plo,
+                                                width, pacc, pbm);
       __syncthreads();
       // epilogue of the panel: thread tid owns columns plo + 16 tid .. + 15
       const double thr = even ? (double)prune * scum * (1.0 - 1.0 / 1024.0) : -HUGE_VAL;
