@@ -183,10 +183,12 @@ int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg
  * FP32 only (dtype SPG_F32); inflation exponent r in 1..8; n <= 2^24
  * (SPG_ERR_UNSUPPORTED above).  X must be canonical (columns ascending
  * within a row, no repeats) with finite values, as MCL iterates on a
- * stochastic matrix and this call's own output is canonical: rows with more
- * products than an LDS table holds are swept in column order and rely on
- * it.  Such rows accumulate exactly-rounded products in 64-bit fixed point
- * scaled per row, so their sums do not depend on the order of the adds. */
+ * stochastic matrix and this call's own output is canonical: rows whose
+ * columns do not fit the largest LDS table are swept in column order and
+ * rely on it.  Such rows accumulate exactly-rounded products in 64-bit fixed
+ * point scaled per row, so their sums do not depend on the order of the
+ * adds; rows held in an LDS table (up to twice that table's product bin)
+ * add in FP32, in no fixed order. */
 int spgemm_mcl_workspace_size(int32_t n, int32_t topk, size_t *bytes);
 int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune,
                          int32_t topk, int32_t *Y_row_ptr, int32_t *Y_col_idx,

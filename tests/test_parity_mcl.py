@@ -167,3 +167,21 @@ def test_handover_path_forced(B):
     t.max_window = 1
     got = B.mcl_iteration(B.to_device(X), 2, 1e-4, 1000, plan=B.Plan(tuning=t)).to_host()
     _check_step(X, got, 2, 1e-4, 1000)
+
+
+@pytest.mark.parametrize("window", [0, 1])
+def test_rows_past_the_largest_table(B, window):
+    """Rows of 8k..16k products (one bin past the largest LDS table) whose
+    columns repeat (n = 4000) fit that table (default window) or overflow it
+    and go to the column-panel kernel (one-slot window): same results."""
+    n = 4000
+    X = _heavy_input(n, dense_rows=(3, 1999, 3999), width=1500, seed=47)
+    bl = np.diff(X.indptr)
+    for i in (3, 1999, 3999):
+        c, _ = X.row(i)
+        assert 8192 < int(bl[c].sum()) <= 16384
+    t = B.default_tuning()
+    if window:
+        t.max_window = window
+    got = B.mcl_iteration(B.to_device(X), 2, 1e-4, 1000, plan=B.Plan(tuning=t)).to_host()
+    _check_step(X, got, 2, 1e-4, 1000, np.array([3, 1999, 3999] + list(range(0, n, 37))))
