@@ -814,6 +814,7 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
 // A row with more products than the staging area holds takes that dense
 // path (the slot's memory as accumulator, the panel as bitmap when n fits).
 constexpr int kRngMax = 1024;  // column ranges a row may span
+constexpr int kRngBuf = 64;    // at most this many ranges get an LDS staging buffer
 
 template <typename VT>
 __device__ void heavy_dense_row(const Problem *__restrict__ pr, int i, int lS, Stage<VT> st,
@@ -867,6 +868,7 @@ __global__ __launch_bounds__(1024) void k_num_heavy_rng(
   uint32_t *pmap = reinterpret_cast<uint32_t *>(panel + W);     // W / 32 words
   __shared__ int rstart[kRngMax + 1];  // range segment starts (exclusive scan of the counts)
   __shared__ int rpos[kRngMax];        // counts, then the next free position of each segment
+  __shared__ int bcnt[kRngBuf];        // products in each range's LDS buffer
   __shared__ int wtot[16];
   __shared__ int sb[1024], sl[1024];
   __shared__ VT sa[1024];
@@ -916,13 +918,40 @@ __global__ __launch_bounds__(1024) void k_num_heavy_rng(
                           cval, hdr);
       continue;
     }
-    // 3. every product into its range's segment
+    // 3. every product into its range's segment.  With few ranges the idle
+    // panel holds a buffer per range, flushed to the segment with coalesced
+    // stores; products past a full buffer go to the segment directly.
+    if (R <= kRngBuf)
+      for (int r = tid; r < R; r += 1024) bcnt[r] = 0;
+    __syncthreads();
+    const int bcap = R <= kRngBuf ? (int)(((size_t)W * sizeof(VT) / (4 + sizeof(VT)) / R) & ~1) : 0;
+    int32_t *bufc = reinterpret_cast<int32_t *>(panel);
+    VT *bufv = reinterpret_cast<VT *>(bufc + (size_t)R * bcap);
     auto fput = each_product([&](int col, VT v) {
-      const int p = atomicAdd(&rpos[col >> log2W], 1);
-      scol[p] = col;
-      sval[p] = v;
+      const int r = col >> log2W;
+      const int b = bcap > 0 ? atomicAdd(&bcnt[r], 1) : 0;
+      if (b < bcap) {
+        bufc[r * bcap + b] = col;
+        bufv[r * bcap + b] = v;
+      } else {
+        const int p = atomicAdd(&rpos[r], 1);
+        scol[p] = col;
+        sval[p] = v;
+      }
     });
     for_each_product<true, true, 1024, kUnroll, VT>(pr, i, true, tid, lS, st, fput);
+    __syncthreads();
+    if (bcap > 0) {
+      for (int r = 0; r < R; ++r) {  // buffered products after the direct ones
+        const int nb = min(bcnt[r], bcap), base = rpos[r];
+        for (int t = tid; t < nb; t += 1024) {
+          scol[base + t] = bufc[r * bcap + t];
+          sval[base + t] = bufv[r * bcap + t];
+        }
+      }
+      __syncthreads();
+      for (int c = tid; c < W; c += 1024) panel[c] = VT(0);  // the panel starts clear
+    }
     __threadfence();  // the staged pairs are read back by other threads of the block
     __syncthreads();
     // 4. the ranges in column order
@@ -985,8 +1014,8 @@ static size_t heavy_slot_bytes(int n) { return ((size_t)(n > 1 ? n : 1) + 4) * 8
 // staged entries).
 template <typename VT>
 static size_t heavy_rng_static_lds() {
-  return (size_t)(kRngMax + 1) * 4 + (size_t)kRngMax * 4 + 16 * 4 + (size_t)1024 * (8 + sizeof(VT)) +
-         256;  // alignment padding
+  return (size_t)(kRngMax + 1) * 4 + (size_t)kRngMax * 4 + (size_t)kRngBuf * 4 + 16 * 4 +
+         (size_t)1024 * (8 + sizeof(VT)) + 256;  // alignment padding
 }
 
 // A heavy row's column bitmap lives in LDS when it fits one block.
