@@ -59,6 +59,28 @@ def test_stage_graph_fp32_against_oracle(B):
         assert_same_csr(g.result().to_host(), ref, S, np.float32, what="graph")
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_stage_graph_power_law_heavy_rows(B, dtype):
+    """R-MAT rows (scale 15, edge factor 16) split into 8 uneven inner blocks:
+    hub rows beyond every LDS table, empty rows and all LDS bins, captured
+    once and replayed; every replay matches the oracle (heavy rows add in
+    no fixed order, so replays are compared by tolerance, not bit for bit)."""
+    from paper_2603_21444_amd.graph import StageGraph
+    n = 1 << 15
+    A = synth.rmat_csr(15, 16, seed=23, dtype=dtype, values="normal")
+    Bm = synth.varnnz_csr(n, n, 4, 32, 23, dtype, "normal", stream=3)
+    f64 = lambda M: M.with_data(M.data.astype(np.float64))
+    ub = oracle.rowub(f64(A), f64(Bm))
+    assert ub.max() > 20000 and (ub == 0).any()
+    ref, S = oracle.spgemm(f64(A), f64(Bm), with_abs=True)
+    bounds = synth.column_blocks(n, 8, n // 16, n // 4, 23)
+    dp = [(B.to_device(a), B.to_device(b)) for a, b in synth.split_inner(A, Bm, bounds)]
+    g = StageGraph(dp)
+    for rep in range(3):
+        g.replay()
+        assert_same_csr(g.result().to_host(), ref, S, dtype, what=f"power-law graph, replay {rep}")
+
+
 def test_stage_graph_capacity_error_surfaces(B):
     from paper_2603_21444_amd.graph import StageGraph
     pairs = _pairs(np.float32, "normal", seed=7, K=3)
