@@ -42,10 +42,55 @@ struct RowHead {
 
 // Products of entries [0, nE) staged in LDS, S lanes per entry, handed to
 // ins.batch<U> (same enumeration as for_each_product).
+// p[0..3] with one 16-byte load (p needs only 4-byte alignment)
+__device__ __forceinline__ int4 load_int4(const SPG_GLOBAL int32_t *p) {
+  int4 v;
+  __builtin_memcpy(&v, p, sizeof(v));
+  return v;
+}
+
+// Columns of entries [0, nE) for the count with four lanes per entry: each
+// lane takes four consecutive elements of its entry's B row per pass, one
+// 16-byte load for all four (a row's last partial group reads element by
+// element from in-range positions).
+template <typename F>
+__device__ __forceinline__ void enum_cols_v4(const SPG_GLOBAL int32_t *bcol, int nE, int lane,
+                                             const int *sb, const int *sl, F &ins) {
+  const int sg = lane >> 2, q0 = 4 * (lane & 3);
+  for (int t0 = sg; t0 < nE; t0 += kWave / 4) {
+    const int b0 = sb[t0], len = sl[t0];
+    for (int q = q0; q < len; q += 16) {
+      int c[4];
+      const float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (q + 4 <= len) {
+        const int4 cc = load_int4(bcol + b0 + q);
+        c[0] = cc.x;
+        c[1] = cc.y;
+        c[2] = cc.z;
+        c[3] = cc.w;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int qq = q + t < len ? q + t : q;
+          c[t] = bcol[b0 + qq];
+          c[t] = q + t < len ? c[t] : -1;
+        }
+      }
+      ins.template batch<4>(c, v);
+    }
+  }
+}
+
 template <bool VALUES, int U, typename VT, typename F>
 __device__ __forceinline__ void enum_staged(const SPG_GLOBAL int32_t *bcol,
                                             const SPG_GLOBAL VT *bval, int nE, int lane, int lS,
                                             const int *sb, const int *sl, const VT *sa, F &ins) {
+  if constexpr (!VALUES) {
+    if (lS == 2) {
+      enum_cols_v4(bcol, nE, lane, sb, sl, ins);
+      return;
+    }
+  }
   const int S = 1 << lS, ES = kWave >> lS, sg = lane >> lS, q0 = lane & (S - 1);
   for (int t0 = sg; t0 < nE; t0 += ES * U) {
     // all LDS reads first, then all global loads, then the products: no
