@@ -88,8 +88,23 @@ int spgemm_workspace_size(int32_t m, int32_t n, int32_t kmax, size_t *bytes);
 
 /* Status word that device kernels raise in capture-safe mode (overflow,
  * capacity), read back on the host (synchronises the plan's last stream).
- * *device_status_host receives an spg_status. */
+ * *device_status_host receives an spg_status.
+ * The word lives in the workspace header.  Eager calls clear it when they
+ * start.  Capture-safe calls clear it only the first time the plan uses a
+ * workspace; afterwards it is sticky: once raised, every later kernel of
+ * every capture-safe call on that workspace exits without touching its
+ * operands or outputs, so an error raised by any call of a captured
+ * sequence (a stage graph, several MCL iterations) is still there at the
+ * end of the sequence and no later call reads an output that was never
+ * written. */
 int spgemm_plan_status(spg_plan plan, int32_t *device_status_host);
+
+/* Queue a clear of the status word of the plan's current workspace on
+ * `stream` (capture-safe: one small kernel, no host synchronisation).  A
+ * captured sequence starts with it so that every replay reports only its
+ * own errors.  SPG_ERR_WORKSPACE if the plan has not been given a workspace
+ * yet. */
+int spgemm_plan_clear_status(spg_plan plan, void *stream);
 
 /* Last known nnz of the plan's output (after a synchronising symbolic call
  * or after spgemm_plan_status), and the number of scalar products. */
@@ -167,6 +182,30 @@ int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg
                     spg_dtype dtype, void *dA_vals, void *dB_vals, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Permutation B = P_r A P_c^T, i.e. B[row_perm[i], col_perm[j]] = A[i, j]
+ * (§5.3: the rows and columns of a structured matrix are permuted uniformly
+ * at random as a light preprocessing step, which turns diagonal bands into
+ * unstructured sparsity; row_perm == col_perm is the symmetric permutation,
+ * under which (P A P^T)^2 = P A^2 P^T).
+ *   A          CSR, any column order; nrows m, ncols n.
+ *   row_perm   device int32 [m], a permutation of 0..m-1, or NULL (identity).
+ *   col_perm   device int32 [n], a permutation of 0..n-1, or NULL (identity).
+ *   B_row_ptr  device [m+1], written.
+ *   B_col_idx  device [nnz(A)], written, every row in ascending order.
+ *   B_vals     device [nnz(A)] of dtype, written, or NULL (pattern only).
+ *   workspace  device, at least spgemm_permute_workspace_size(m, n).
+ * Capture-safe: nothing is read back.  An array that is not a permutation
+ * raises SPG_ERR_INVALID in the plan's device status word
+ * (spgemm_plan_status; cleared on the plan's first use of the workspace,
+ * sticky afterwards) and nothing more is written.  Values are copied, not
+ * computed. */
+int spgemm_permute_workspace_size(int32_t m, int32_t n, size_t *bytes);
+int spgemm_permute(spg_plan plan, const spg_csr *A, const int32_t *row_perm,
+                   const int32_t *col_perm, spg_dtype dtype, int32_t *B_row_ptr,
+                   int32_t *B_col_idx, void *B_vals, void *workspace, size_t ws_bytes,
+                   void *stream);
+
+/* ------------------------------------------------------------------------
  * One Markov-clustering iteration (§5.7) on X = M^T (row c of X is
  * column c of M, so (M M)^T = X X):
  *   E = X X; e <- e^r; divide each row by its sum; drop e < prune;
@@ -176,9 +215,12 @@ int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg
  *   Y_row_ptr  device [n+1], written.
  *   Y_col_idx, Y_vals  device, capacity entries each (capacity >= the
  *              output nnz; n*min(topk,n) always suffices), written.
- *   Y_nnz_host non-NULL: synchronises and returns nnz(Y); NULL: capture-
- *              safe (overflow of capacity -> SPG_ERR_CAPACITY in the device
- *              status word).
+ *   capacity   entries of Y_col_idx / Y_vals; an output larger than it
+ *              raises SPG_ERR_CAPACITY and nothing is written to them.
+ *              Eager mode may pass -1 (unchecked: the caller sized the
+ *              buffers for n*min(topk,n)).
+ *   Y_nnz_host non-NULL: synchronises and returns nnz(Y) (or the error);
+ *              NULL: capture-safe, errors go to the device status word.
  *   workspace  device, at least spgemm_mcl_workspace_size(n, topk).
  * FP32 only (dtype SPG_F32); inflation exponent r in 1..8; n <= 2^24
  * (SPG_ERR_UNSUPPORTED above).  X must be canonical (columns ascending

@@ -14,8 +14,12 @@ Functions and the paper passages they follow:
                (§3.3.1, Alg. 1 and Eq. (1)/(2))
   merge     -- C = sum_k C_k, union pattern, values added (§4.4)
   mcl_rows  -- one Markov-clustering iteration on selected rows of X = M^T
-               (§5.7; step order of the synthetic workload)
+               (§5.7; order="workload": inflate, normalise, prune, top-k,
+               renormalise; order="paper": normalise, prune, element-wise
+               power, the order the paper describes for its runs)
   backward  -- dA, dB of L = <W, C> at fixed sparsity (not in the paper)
+  permute   -- B[prow[i], pcol[j]] = A[i, j], rows in ascending column
+               order (§5.3: random permutation as preprocessing)
 """
 from __future__ import annotations
 
@@ -48,7 +52,8 @@ def lib():
         L = C.CDLL(path)
         for name in ["oracle_rowub", "oracle_spgemm_count", "oracle_spgemm_fill",
                      "oracle_batched_count", "oracle_batched_fill", "oracle_merge",
-                     "oracle_mcl_rows", "oracle_backward", "oracle_num_threads"]:
+                     "oracle_mcl_rows", "oracle_mcl_rows_paper", "oracle_backward", "oracle_permute",
+                     "oracle_num_threads"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -185,9 +190,11 @@ def merge(parts, with_abs: bool = False):
     return (Cm, cabs) if with_abs else Cm
 
 
-def mcl_rows(X, rows, r: int = 2, prune: float = 1e-4, topk: int = 1000):
+def mcl_rows(X, rows, r: int = 2, prune: float = 1e-4, topk: int = 1000,
+             order: str = "workload", flat: bool = False):
     """One MCL iteration on the given rows of X = M^T.  Returns
-    (counts[nsel], cols list, vals list) with rows in canonical order."""
+    (counts[nsel], cols list, vals list) with rows in canonical order, or
+    with flat=True (counts, all columns, all values) concatenated."""
     n = X.shape[0]
     rows = _i64(rows)
     cap = int(min(topk, n))
@@ -196,23 +203,29 @@ def mcl_rows(X, rows, r: int = 2, prune: float = 1e-4, topk: int = 1000):
     cnt = np.zeros(nsel, dtype=np.int32)
     oc = np.zeros(max(nsel * cap, 1), dtype=np.int32)
     ov = np.zeros(max(nsel * cap, 1), dtype=np.float64)
-    _check(lib().oracle_mcl_rows(_I64(n), _p(xrp), _p(xcol), _p(xval), _I64(nsel), _p(rows),
-                                 C.c_int(r), C.c_double(prune), _I64(topk), _I64(cap),
-                                 _p(cnt), _p(oc), _p(ov)))
+    if order == "workload":
+        fn = lib().oracle_mcl_rows
+    elif order == "paper":
+        fn = lib().oracle_mcl_rows_paper
+    else:
+        raise ValueError(f"unknown MCL step order {order!r}")
+    _check(fn(_I64(n), _p(xrp), _p(xcol), _p(xval), _I64(nsel), _p(rows), C.c_int(r),
+              C.c_double(prune), _I64(topk), _I64(cap), _p(cnt), _p(oc), _p(ov)))
+    if flat:
+        keep = (np.arange(cap)[None, :] < cnt[:, None]).reshape(-1)
+        return cnt, oc[:nsel * cap][keep], ov[:nsel * cap][keep]
     cols = [oc[t * cap: t * cap + cnt[t]].copy() for t in range(nsel)]
     vals = [ov[t * cap: t * cap + cnt[t]].copy() for t in range(nsel)]
     return cnt, cols, vals
 
 
-def mcl_step(X, r: int = 2, prune: float = 1e-4, topk: int = 1000):
+def mcl_step(X, r: int = 2, prune: float = 1e-4, topk: int = 1000, order: str = "workload"):
     """One MCL iteration on every row; returns the new X as CSR (FP64)."""
     n = X.shape[0]
-    cnt, cols, vals = mcl_rows(X, np.arange(n), r, prune, topk)
+    cnt, cols, vals = mcl_rows(X, np.arange(n), r, prune, topk, order, flat=True)
     indptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(cnt, out=indptr[1:])
-    indices = np.concatenate(cols) if n else np.zeros(0, np.int32)
-    data = np.concatenate(vals) if n else np.zeros(0)
-    return _csr((n, n), indptr, indices.astype(np.int32), data)
+    return _csr((n, n), indptr, cols.astype(np.int32), vals)
 
 
 def backward(A, B, Cpat, W):
@@ -229,3 +242,19 @@ def backward(A, B, Cpat, W):
                                  _p(brp), _p(bcol), _p(bval), _p(crp), _p(ccol), _p(w),
                                  _p(da), _p(db)))
     return da, db
+
+
+def permute(A, prow=None, pcol=None):
+    """B[prow[i], pcol[j]] = A[i, j] (None = identity), rows sorted."""
+    m, n = A.shape
+    arp, acol = _i64(A.indptr), _i32(A.indices)
+    aval = None if A.data is None else _f64(A.data)
+    pr = None if prow is None else _i32(prow)
+    pc = None if pcol is None else _i32(pcol)
+    brp = np.zeros(m + 1, dtype=np.int64)
+    bcol = np.zeros(max(int(arp[-1]), 1), dtype=np.int32)
+    bval = None if aval is None else np.zeros(max(int(arp[-1]), 1), dtype=np.float64)
+    _check(lib().oracle_permute(_I64(m), _I64(n), _p(arp), _p(acol), _p(aval), _p(pr), _p(pc),
+                                _p(brp), _p(bcol), _p(bval)))
+    nnz = int(brp[-1])
+    return _csr((m, n), brp, bcol[:nnz], None if bval is None else bval[:nnz])

@@ -17,8 +17,10 @@
  *    into one sparse matrix (union of patterns, values added).
  *  - §5.7: Markov clustering iterates expansion (squaring by SpGEMM),
  *    column normalisation, pruning of small entries and an element-wise
- *    power (inflation).  The workload variant checked here holds X = M^T so
- *    that rows of X are columns of M.
+ *    power (inflation).  Both step orders are here: the synthetic
+ *    workload's (inflate, normalise, prune, top-k, renormalise) and the
+ *    paper's own (normalise, prune, element-wise power).  Both hold
+ *    X = M^T so that rows of X are columns of M.
  *  - Differentiation at fixed sparsity (not in the paper): for the bilinear
  *    loss L = sum_{(i,j) in S(C)} W_ij C_ij, dL/da_ik = sum_j W_ij b_kj over
  *    (k,j) in S(B), dL/db_kj = sum_i a_ik W_ij over (i,k) in S(A).
@@ -362,6 +364,164 @@ int oracle_mcl_rows(int64_t n, const int64_t *xrp, const int32_t *xcol, const do
     }
     free(mark); free(touched); free(acc); free(cand);
   }
+  return err;
+}
+
+/* ---------------------------------------------------------------------- */
+/* One Markov-clustering iteration in the order the paper describes for its
+ * own runs (§5.7): expansion by squaring, normalisation of the columns,
+ * pruning of the entries below a threshold, then an element-wise power of
+ * what remains (the paper squares; r is the exponent).  The columns are not
+ * normalised again afterwards: the next iteration's normalisation does it.
+ * On selected rows of X = M^T:
+ *   1. E = X X;
+ *   2. divide the row by its sum;
+ *   3. prune: drop entries with e < prune (strictly less);
+ *   4. if more than topk remain, keep the topk largest, ties going to the
+ *      smaller column (with prune > 0 at most 1/prune entries can remain, so
+ *      topk >= 1/prune leaves this step inactive);
+ *   5. if nothing remains, keep the largest entry of step 2 (ties to the
+ *      smaller column);
+ *   6. e <- e^r for every kept entry.
+ * Same output layout as oracle_mcl_rows. */
+int oracle_mcl_rows_paper(int64_t n, const int64_t *xrp, const int32_t *xcol,
+                          const double *xval, int64_t nsel, const int64_t *rows, int r,
+                          double prune, int64_t topk, int64_t cap, int32_t *out_cnt,
+                          int32_t *out_col, double *out_val) {
+  int err = ORC_OK;
+  if (r < 1 || topk < 1) return ORC_INVALID;
+#pragma omp parallel
+  {
+    int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    double *acc = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    vj_t *cand = (vj_t *)malloc(sizeof(vj_t) * (size_t)(n > 0 ? n : 1));
+    int ok = mark && touched && acc && cand;
+    if (!ok) {
+      SETERR(ORC_NOMEM);
+    } else {
+      for (int64_t j = 0; j < n; ++j) mark[j] = -1;
+    }
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nsel; ++t) {
+      if (!ok) continue;
+      int64_t i = rows[t];
+      if (i < 0 || i >= n) { SETERR(ORC_INVALID); continue; }
+      int64_t nt = 0;
+      /* 1. expansion */
+      for (int64_t p = xrp[i]; p < xrp[i + 1]; ++p) {
+        int32_t kk = xcol[p];
+        double a = xval[p];
+        for (int64_t q = xrp[kk]; q < xrp[kk + 1]; ++q) {
+          int32_t j = xcol[q];
+          if (mark[j] != (int32_t)t) { mark[j] = (int32_t)t; touched[nt++] = j; acc[j] = 0.0; }
+          acc[j] += a * xval[q];
+        }
+      }
+      int32_t *oc = out_col + t * cap;
+      double *ov = out_val + t * cap;
+      if (nt == 0) { out_cnt[t] = 0; continue; }
+      qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+      /* 2. normalisation */
+      double s = 0.0;
+      for (int64_t u = 0; u < nt; ++u) s += acc[touched[u]];
+      int64_t best = 0;
+      for (int64_t u = 0; u < nt; ++u) {
+        acc[touched[u]] /= s;
+        if (acc[touched[u]] > acc[touched[best]]) best = u; /* first max = smallest col */
+      }
+      /* 3. prune */
+      int64_t nc = 0;
+      for (int64_t u = 0; u < nt; ++u) {
+        double e = acc[touched[u]];
+        if (!(e < prune)) { cand[nc].v = e; cand[nc].j = touched[u]; ++nc; }
+      }
+      /* 4. top-k, ties to the smaller column */
+      if (nc > topk) {
+        qsort(cand, (size_t)nc, sizeof(vj_t), cmp_vj_desc);
+        nc = topk;
+        for (int64_t u = 0; u < nc; ++u) touched[u] = cand[u].j;
+        qsort(touched, (size_t)nc, sizeof(int32_t), cmp_i32);
+        for (int64_t u = 0; u < nc; ++u) { cand[u].j = touched[u]; cand[u].v = acc[touched[u]]; }
+      }
+      /* 5. never empty */
+      if (nc == 0) { cand[0].j = touched[best]; cand[0].v = acc[touched[best]]; nc = 1; }
+      if (nc > cap) { SETERR(ORC_INVALID); continue; }
+      /* 6. element-wise power of the kept entries */
+      for (int64_t u = 0; u < nc; ++u) {
+        double e = cand[u].v, p = e;
+        for (int q = 1; q < r; ++q) p *= e;
+        oc[u] = cand[u].j;
+        ov[u] = p;
+      }
+      out_cnt[t] = (int32_t)nc;
+    }
+    free(mark); free(touched); free(acc); free(cand);
+  }
+  return err;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Permutation of rows and columns (§5.3: a structured matrix is permuted
+ * uniformly at random before the product): B[prow[i], pcol[j]] = A[i, j],
+ * each row of B in ascending column order.  prow / pcol NULL means the
+ * identity; an array that is not a permutation is an error (1). */
+typedef struct { int32_t j; double v; } jv_t;
+
+static int cmp_jv(const void *a, const void *b) {
+  int32_t x = ((const jv_t *)a)->j, y = ((const jv_t *)b)->j;
+  return (x > y) - (x < y);
+}
+
+static int is_permutation(int64_t n, const int32_t *p) {
+  if (!p) return 1;
+  char *seen = (char *)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!seen) return 0;
+  int ok = 1;
+  for (int64_t i = 0; i < n && ok; ++i) {
+    if (p[i] < 0 || p[i] >= n || seen[p[i]]) ok = 0;
+    else seen[p[i]] = 1;
+  }
+  free(seen);
+  return ok;
+}
+
+int oracle_permute(int64_t m, int64_t n, const int64_t *arp, const int32_t *acol,
+                   const double *aval, const int32_t *prow, const int32_t *pcol,
+                   int64_t *brp, int32_t *bcol, double *bval) {
+  if (!is_permutation(m, prow) || !is_permutation(n, pcol)) return ORC_INVALID;
+  int64_t *from = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+  if (!from) return ORC_NOMEM;
+  /* new row prow[i] comes from old row i */
+  for (int64_t i = 0; i < m; ++i) from[prow ? prow[i] : i] = i;
+  brp[0] = 0;
+  for (int64_t r = 0; r < m; ++r) brp[r + 1] = brp[r] + (arp[from[r] + 1] - arp[from[r]]);
+  int err = ORC_OK;
+  jv_t *row = NULL;
+  int64_t cap = 0;
+  for (int64_t r = 0; r < m && err == ORC_OK; ++r) {
+    int64_t i = from[r], len = arp[i + 1] - arp[i];
+    if (len > cap) {
+      free(row);
+      cap = len;
+      row = (jv_t *)malloc(sizeof(jv_t) * (size_t)cap);
+      if (!row) { err = ORC_NOMEM; break; }
+    }
+    for (int64_t t = 0; t < len; ++t) {
+      int32_t j = acol[arp[i] + t];
+      if (j < 0 || j >= n) { err = ORC_INVALID; break; }
+      row[t].j = pcol ? pcol[j] : j;
+      row[t].v = aval ? aval[arp[i] + t] : 0.0;
+    }
+    if (err) break;
+    qsort(row, (size_t)len, sizeof(jv_t), cmp_jv);
+    for (int64_t t = 0; t < len; ++t) {
+      bcol[brp[r] + t] = row[t].j;
+      if (bval) bval[brp[r] + t] = row[t].v;
+    }
+  }
+  free(row);
+  free(from);
   return err;
 }
 

@@ -124,3 +124,15 @@ def _from_json(d: dict) -> binding.SpgTuning:
     t.heavy_slots = d["heavy_slots"]
     t.max_window = d["max_window"]
     return t
+
+
+def describe(t: binding.SpgTuning, bins=range(1, 12)) -> dict:
+    """Compact record of a tuning for reports: per LDS bin, lanes per row,
+    lanes per A entry (numeric, symbolic)."""
+    d = binding.default_tuning()
+    out = {}
+    for b in bins:
+        cur = (t.lanes[b], t.sub[b], t.sym_sub[b])
+        if cur != (d.lanes[b], d.sub[b], d.sym_sub[b]):
+            out[str(b)] = list(cur)
+    return {"changed_bins": out, "heavy_slots": t.heavy_slots, "max_window": t.max_window}

@@ -31,9 +31,10 @@ SPG_NBINS = 16
 # every symbol the header declares (checked by the CPU test suite)
 EXPORTS = [
     "spgemm_plan_create", "spgemm_plan_destroy", "spgemm_workspace_size",
-    "spgemm_plan_status", "spgemm_plan_info", "spgemm_status_string",
+    "spgemm_plan_status", "spgemm_plan_clear_status", "spgemm_plan_info", "spgemm_status_string",
     "spgemm_symbolic", "spgemm_numeric", "spgemm_merge", "spgemm_backward",
     "spgemm_mcl_workspace_size", "spgemm_mcl_iteration",
+    "spgemm_permute_workspace_size", "spgemm_permute",
     "spgemm_default_tuning", "spgemm_plan_set_tuning", "spgemm_plan_bins",
 ]
 
@@ -73,6 +74,7 @@ def lib():
             "spgemm_plan_destroy": (None, [P]),
             "spgemm_workspace_size": (C.c_int, [I32, I32, I32, C.POINTER(C.c_size_t)]),
             "spgemm_plan_status": (C.c_int, [P, C.POINTER(I32)]),
+            "spgemm_plan_clear_status": (C.c_int, [P, P]),
             "spgemm_plan_info": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64)]),
             "spgemm_status_string": (C.c_char_p, [C.c_int]),
             "spgemm_symbolic": (C.c_int, [P, I32, PC, PC, P, C.POINTER(I64), I64, P, C.c_size_t, P]),
@@ -83,6 +85,8 @@ def lib():
             "spgemm_mcl_workspace_size": (C.c_int, [I32, I32, C.POINTER(C.c_size_t)]),
             "spgemm_mcl_iteration": (C.c_int, [P, PC, I32, C.c_float, I32, P, P, P, I64,
                                                C.POINTER(I64), P, C.c_size_t, P]),
+            "spgemm_permute_workspace_size": (C.c_int, [I32, I32, C.POINTER(C.c_size_t)]),
+            "spgemm_permute": (C.c_int, [P, PC, P, P, C.c_int, P, P, P, P, C.c_size_t, P]),
             "spgemm_default_tuning": (C.c_int, [C.POINTER(SpgTuning)]),
             "spgemm_plan_set_tuning": (C.c_int, [P, C.POINTER(SpgTuning)]),
             "spgemm_plan_bins": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
@@ -223,6 +227,10 @@ class Plan:
         _check(lib().spgemm_plan_status(self.h, C.byref(s)), "spgemm_plan_status")
         return int(s.value)
 
+    def clear_status(self, stream=None):
+        """Queue a clear of the device status word (capture-safe)."""
+        _check(lib().spgemm_plan_clear_status(self.h, _stream(stream)), "spgemm_plan_clear_status")
+
     def bins(self):
         """(symbolic bin counts, numeric bin counts) after an eager symbolic call."""
         s = (C.c_int32 * SPG_NBINS)()
@@ -343,11 +351,12 @@ def mcl_workspace_size(n: int, topk: int) -> int:
 
 def mcl_iteration(X: DeviceCSR, r: int = 2, prune: float = 1e-4, topk: int = 1000,
                   plan: Plan | None = None, out=None, stream=None,
-                  capture: bool = False) -> DeviceCSR:
+                  capture: bool = False, capacity: int | None = None) -> DeviceCSR:
     """One Markov-clustering iteration on X = M^T (FP32).  `out` may hold
-    preallocated (row_ptr, col_idx, vals) of capacity n*min(topk, n).  With
-    capture=True nothing is read back (graph-capturable); the result then
-    spans the whole capacity and its length is row_ptr[n]."""
+    preallocated (row_ptr, col_idx, vals) of `capacity` entries (default
+    n*min(topk, n), which always suffices).  With capture=True nothing is
+    read back (graph-capturable); the result then spans the whole capacity
+    and its length is row_ptr[n]."""
     torch = _torch()
     plan = plan or Plan()
     n = X.shape[0]
@@ -355,7 +364,7 @@ def mcl_iteration(X: DeviceCSR, r: int = 2, prune: float = 1e-4, topk: int = 100
     need = mcl_workspace_size(n, topk)
     if plan.ws is None or plan.ws.numel() < need:
         plan.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    cap = n * min(topk, n)
+    cap = n * min(topk, n) if capacity is None else int(capacity)
     if out is None:
         out = (torch.empty(n + 1, dtype=torch.int32, device=dev),
                torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
@@ -371,3 +380,35 @@ def mcl_iteration(X: DeviceCSR, r: int = 2, prune: float = 1e-4, topk: int = 100
         return DeviceCSR((n, n), rp, col, vals)
     k = int(nnz.value)
     return DeviceCSR((n, n), rp, col[:k], vals[:k])
+
+
+def permute_workspace_size(m: int, n: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().spgemm_permute_workspace_size(m, n, C.byref(b)), "spgemm_permute_workspace_size")
+    return int(b.value)
+
+
+def permute(A: DeviceCSR, row_perm=None, col_perm=None, plan: Plan | None = None,
+            stream=None, out=None) -> DeviceCSR:
+    """B[row_perm[i], col_perm[j]] = A[i, j] on the GPU (int32 device
+    permutations or None for the identity; rows of B come out in ascending
+    column order).  Errors (an array that is not a permutation) go to the
+    plan's device status word."""
+    torch = _torch()
+    plan = plan or Plan()
+    m, n = A.shape
+    dev = A.row_ptr.device
+    need = permute_workspace_size(m, n)
+    if plan.ws is None or plan.ws.numel() < need:
+        plan.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = (torch.empty(m + 1, dtype=torch.int32, device=dev),
+               torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev),
+               None if A.vals is None else torch.empty(max(A.nnz, 1), dtype=A.vals.dtype, device=dev))
+    rp, col, vals = out
+    a = A.spg()
+    dt = dtype_code(A.vals.dtype) if A.vals is not None else SPG_F32
+    _check(lib().spgemm_permute(plan.h, C.byref(a), _ptr(row_perm), _ptr(col_perm), dt, _ptr(rp),
+                                _ptr(col), _ptr(vals), _ptr(plan.ws), plan.ws.numel(),
+                                _stream(stream)), "spgemm_permute")
+    return DeviceCSR((m, n), rp, col[:A.nnz], None if vals is None else vals[:A.nnz])

@@ -34,12 +34,18 @@ struct spg_plan_s {
   int32_t *crp = nullptr;
   hipStream_t stream = nullptr;
   WsHeader *host_hdr = nullptr;  // pinned readback buffer
+  // workspace whose status word this plan has cleared at least once: a
+  // capture-safe call clears it only on first use of a workspace, so an
+  // error raised by one call of a captured sequence reaches the end of it
+  const void *status_ws = nullptr;
 };
 
 namespace spg {
 
 static std::mutex g_dev_mu;
-static std::vector<DevInfo> g_dev;
+constexpr int kMaxDevices = 64;
+static DevInfo g_dev[kMaxDevices];  // fixed table: no allocation on any call
+static int g_ndev = 0;
 
 // Largest bin whose table fits one block (one row per block, 1024 lanes).
 static int maxbin_for(size_t lds, int pass, size_t vbytes) {
@@ -57,8 +63,8 @@ const DevInfo &dev_info() {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> g(g_dev_mu);
-  for (const DevInfo &d : g_dev)
-    if (d.device == dev) return d;
+  for (int t = 0; t < g_ndev; ++t)
+    if (g_dev[t].device == dev) return g_dev[t];
   DevInfo d;
   d.device = dev;
   int v = 0;
@@ -82,8 +88,12 @@ const DevInfo &dev_info() {
   (void)configure_mcl_lds(d.lds_per_block);
   (void)configure_wave_lds(d.lds_per_block);
   (void)hipGetLastError();
-  g_dev.push_back(d);
-  return g_dev.back();
+  if (g_ndev == kMaxDevices) {  // more devices than the table: reuse the last entry
+    g_dev[kMaxDevices - 1] = d;
+    return g_dev[kMaxDevices - 1];
+  }
+  g_dev[g_ndev] = d;
+  return g_dev[g_ndev++];
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -198,16 +208,21 @@ BinPlan make_binplan(spg_plan p, int maxbin, bool counts_known, const int *count
 // Shared symbolic sequence for products (identity == false) and merges.
 int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr *B,
                  int32_t *C_row_ptr, int64_t *C_nnz_host, int64_t capacity, void *workspace,
-                 size_t ws_bytes, hipStream_t st) {
+                 size_t ws_bytes, hipStream_t st, int heavy_override = 0) {
   const int m = pr.m, n = pr.n;
-  const int heavy = p->tun.heavy_slots > 0 ? p->tun.heavy_slots : default_heavy_slots(n);
+  const int heavy = heavy_override > 0         ? heavy_override
+                    : p->tun.heavy_slots > 0 ? p->tun.heavy_slots
+                                             : default_heavy_slots(n);
   const WsLayout L = ws_layout(m, n, heavy);
   if (!workspace || ws_bytes < L.total) return SPG_ERR_WORKSPACE;
   if (!C_nnz_host && capacity < 0) return SPG_ERR_ARG;
+  const bool eager = C_nnz_host != nullptr;
+  const bool clear = eager || p->status_ws != workspace;
   p->sym_done = false;
   p->counts_known = false;
   p->ws = static_cast<char *>(workspace);
   p->ws_bytes = ws_bytes;
+  p->status_ws = workspace;
   p->L = L;
   p->crp = C_row_ptr;
   p->stream = st;
@@ -220,9 +235,8 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
   char *ws = p->ws;
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   Problem *dpr = reinterpret_cast<Problem *>(ws + L.problem);
-  hipError_t e = launch_setup(pr, dpr, hdr, true, st);
+  hipError_t e = launch_setup(pr, dpr, hdr, true, clear, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
-  const bool eager = C_nnz_host != nullptr;
   if (p->flags & SPG_FLAG_VALIDATE) {
     // every later kernel exits once the status word is raised, so invalid
     // operands are never dereferenced; eagerly the call returns right here
@@ -343,7 +357,7 @@ int run_numeric(spg_plan p, const Problem &pr, spg_dtype dtype, int32_t *C_col_i
   char *ws = p->ws;
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   Problem *dpr = reinterpret_cast<Problem *>(ws + p->L.problem);
-  hipError_t e = launch_setup(pr, dpr, hdr, false, st);
+  hipError_t e = launch_setup(pr, dpr, hdr, false, false, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
   const int maxbin = dtype == SPG_F64 ? D.num_maxbin_f64 : D.num_maxbin_f32;
   BinPlan bp = make_binplan(p, maxbin, p->counts_known, p->num_count);
@@ -391,6 +405,14 @@ int spgemm_plan_status(spg_plan plan, int32_t *device_status_host) {
   plan->nnz = plan->host_hdr->nnz_total;
   plan->products = plan->host_hdr->products_total;
   return SPG_OK;
+}
+
+int spgemm_plan_clear_status(spg_plan plan, void *stream) {
+  if (!plan) return SPG_ERR_ARG;
+  if (!plan->ws) return SPG_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_clear_status(reinterpret_cast<WsHeader *>(plan->ws), st);
+  return hip_status(e);
 }
 
 int spgemm_plan_info(spg_plan plan, int64_t *nnz, int64_t *products) {
@@ -509,13 +531,52 @@ int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg
   char *ws = plan->ws;
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   Problem *dpr = reinterpret_cast<Problem *>(ws + plan->L.problem);
-  hipError_t e = launch_setup(pr, dpr, hdr, false, st);
+  hipError_t e = launch_setup(pr, dpr, hdr, false, false, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
   const int maxbin = dtype == SPG_F64 ? D.num_maxbin_f64 : D.num_maxbin_f32;
   BinPlan bp = make_binplan(plan, maxbin, plan->counts_known, plan->num_count);
   e = launch_backward(dpr, bp, plan->L, ws, dC->row_ptr, dC->col_idx, dC->vals, dA_vals,
                       A->nnz, dB_vals, B->nnz, (int)dtype, st);
   plan->stream = st;
+  return hip_status(e);
+}
+
+int spgemm_permute_workspace_size(int32_t m, int32_t n, size_t *bytes) {
+  if (!bytes || m < 0 || n < 0) return SPG_ERR_ARG;
+  size_t a, b, c, d;
+  *bytes = perm_workspace_bytes(m, n, &a, &b, &c, &d);
+  return SPG_OK;
+}
+
+int spgemm_permute(spg_plan plan, const spg_csr *A, const int32_t *row_perm,
+                   const int32_t *col_perm, spg_dtype dtype, int32_t *B_row_ptr,
+                   int32_t *B_col_idx, void *B_vals, void *workspace, size_t ws_bytes,
+                   void *stream) {
+  if (!plan || !A || !B_row_ptr) return SPG_ERR_ARG;
+  if (dtype != SPG_F32 && dtype != SPG_F64) return SPG_ERR_ARG;
+  if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0 || A->nnz > 0x7fffffffLL) return SPG_ERR_ARG;
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !B_col_idx))) return SPG_ERR_ARG;
+  if (B_vals && A->nnz > 0 && !A->vals) return SPG_ERR_ARG;
+  size_t r0, c0, l0, s0;
+  const size_t need = perm_workspace_bytes(A->nrows, A->ncols, &r0, &c0, &l0, &s0);
+  if (!workspace || ws_bytes < need) return SPG_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool clear = plan->status_ws != workspace;
+  plan->status_ws = workspace;
+  plan->ws = static_cast<char *>(workspace);
+  plan->ws_bytes = ws_bytes;
+  plan->stream = st;
+  plan->sym_done = false;
+  plan->counts_known = false;
+  plan->nnz = A->nnz;
+  plan->products = -1;
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(workspace);
+  Problem pr;
+  std::memset(&pr, 0, sizeof(pr));
+  hipError_t e = launch_setup(pr, reinterpret_cast<Problem *>(plan->ws + 256), hdr, true, clear, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  e = launch_permute(*A, row_perm, col_perm, (int)dtype, B_row_ptr, B_col_idx, B_vals,
+                     plan->ws, st);
   return hip_status(e);
 }
 
@@ -561,10 +622,13 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
   int rc = fill_parts(pr, 1, X, X, false);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool eager = Y_nnz_host != nullptr;
+  const bool clear = eager || plan->status_ws != workspace;
   plan->sym_done = false;
   plan->counts_known = false;
   plan->ws = static_cast<char *>(workspace);
   plan->ws_bytes = ws_bytes;
+  plan->status_ws = workspace;
   plan->L = L;
   plan->stream = st;
   plan->m = plan->n = n;
@@ -575,9 +639,8 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
   Problem *dpr = reinterpret_cast<Problem *>(ws + L.problem);
   int32_t *pcol = reinterpret_cast<int32_t *>(ws + pcol_off);
   float *pval = reinterpret_cast<float *>(ws + pval_off);
-  hipError_t e = launch_setup(pr, dpr, hdr, true, st);
+  hipError_t e = launch_setup(pr, dpr, hdr, true, clear, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
-  const bool eager = Y_nnz_host != nullptr;
   if (plan->flags & SPG_FLAG_VALIDATE) {
     e = launch_validate(X->row_ptr, X->col_idx, n, n, X->nnz, hdr, st);
     if (e != hipSuccess) return SPG_ERR_HIP;
@@ -606,7 +669,7 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
   }
   e = launch_mcl(dpr, bp, L, ws, r, prune, topk, cap, pcol, pval, Y_row_ptr, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
-  e = launch_scan(Y_row_ptr, n, eager ? -1 : capacity, L, ws, st);
+  e = launch_scan(Y_row_ptr, n, capacity, L, ws, st);  // capacity < 0: unchecked
   if (e != hipSuccess) return SPG_ERR_HIP;
   if (eager) {
     rc = read_header(plan, st);

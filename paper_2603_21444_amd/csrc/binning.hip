@@ -14,15 +14,17 @@
 namespace spg {
 
 // ---------------------------------------------------------------------------
-// Setup: copy the problem into the workspace, clear the header.
-__global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset) {
+// Setup: copy the problem into the workspace, clear the header's counters
+// (reset) and the status word (clear_status).  A status word that is not
+// cleared stays raised, so every later kernel of a captured sequence exits.
+__global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset, int clear_status) {
   if (threadIdx.x == 0) *dst = pr;
   if (reset && threadIdx.x < kNB) {
     hdr->bin_count[threadIdx.x] = 0;
     hdr->bin_start[threadIdx.x] = 0;
   }
+  if (clear_status && threadIdx.x == 0) hdr->status = 0;
   if (reset && threadIdx.x == 0) {
-    hdr->status = 0;
     hdr->nnz_total = 0;
     hdr->products_total = 0;
     hdr->bin_start[kNB] = 0;
@@ -233,8 +235,10 @@ __global__ __launch_bounds__(kBinBlock) void k_binscatter(const uint8_t *binid, 
 // (int64 running total; > 2^31-1 raises the overflow status).
 constexpr int kScanTile = 2048;  // 256 threads x 8
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const int32_t *cnt, int m, int64_t *part) {
+__global__ __launch_bounds__(256) void k_scan_reduce(const int32_t *cnt, int m, int64_t *part,
+                                                    const WsHeader *hdr) {
   __shared__ long long ws[4];
+  if (hdr->status) return;  // the counts were never written
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   long long s = 0;
   for (int j = 0; j < 8; ++j) {
@@ -251,6 +255,7 @@ __global__ __launch_bounds__(1024) void k_scan_mid(int64_t *part, int nparts, in
                                                    WsHeader *hdr) {
   __shared__ long long wsum[16];
   __shared__ long long carry;
+  if (hdr->status) return;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int c0 = 0; c0 < nparts; c0 += 1024) {
@@ -285,6 +290,7 @@ __global__ __launch_bounds__(1024) void k_scan_mid(int64_t *part, int nparts, in
 __global__ __launch_bounds__(256) void k_scan_apply(int32_t *rp, int m, const int64_t *part,
                                                     const WsHeader *hdr) {
   __shared__ long long wsum[4];
+  if (hdr->status) return;  // failed earlier or the total overflowed: row_ptr stays as it is
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   // each thread owns 8 consecutive entries
   const int64_t i0 = base + threadIdx.x * 8;
@@ -314,8 +320,18 @@ __global__ __launch_bounds__(256) void k_scan_apply(int32_t *rp, int m, const in
 // Host launchers.
 
 hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool reset,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, pr, dst, hdr, reset ? 1 : 0);
+                        bool clear_status, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, pr, dst, hdr, reset ? 1 : 0,
+                     clear_status ? 1 : 0);
+  return hipGetLastError();
+}
+
+__global__ void k_clear_status(WsHeader *hdr) {
+  if (threadIdx.x == 0) hdr->status = 0;
+}
+
+hipError_t launch_clear_status(WsHeader *hdr, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, hdr);
   return hipGetLastError();
 }
 
@@ -344,7 +360,7 @@ hipError_t launch_scan(int32_t *rp, int m, int64_t capacity, const WsLayout &L, 
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   int64_t *part = reinterpret_cast<int64_t *>(ws + L.scanpart);
   const int nparts = m == 0 ? 1 : (m + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(256), 0, st, rp, m, part);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(256), 0, st, rp, m, part, hdr);
   hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, part, nparts, capacity, hdr);
   hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(256), 0, st, rp, m, part, hdr);
   return hipGetLastError();

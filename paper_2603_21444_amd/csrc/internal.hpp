@@ -57,7 +57,8 @@ struct BinPlan {
 };
 
 hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool reset,
-                        hipStream_t st);
+                        bool clear_status, hipStream_t st);
+hipError_t launch_clear_status(WsHeader *hdr, hipStream_t st);
 hipError_t launch_validate(const int32_t *rp, const int32_t *col, int rows, int ncols,
                            int64_t nnz, WsHeader *hdr, hipStream_t st);
 hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const WsLayout &L, char *ws,
@@ -95,6 +96,13 @@ void launch_num_wave(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int
                      int count, uint32_t mul, int maxwin, bool pack, const int32_t *crp,
                      int32_t *ccol, void *cval, bool f64, int32_t *fb, hipStream_t st);
 hipError_t configure_wave_lds(size_t lds_max);
+
+// Permutation B[prow[i], pcol[j]] = A[i, j] (either array may be NULL:
+// identity).  Workspace regions from perm_workspace_bytes.
+size_t perm_workspace_bytes(int64_t m, int64_t n, size_t *rinv_off, size_t *cinv_off,
+                            size_t *long_off, size_t *scan_off);
+hipError_t launch_permute(const spg_csr &A, const int32_t *prow, const int32_t *pcol, int dtype,
+                          int32_t *brp, int32_t *bcol, void *bval, char *ws, hipStream_t st);
 
 // LDS bytes of one block of the symbolic / numeric kernel of bin b with G
 // lanes per row.

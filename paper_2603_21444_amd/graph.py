@@ -43,7 +43,10 @@ class StageGraph:
             self.record(self.stream)
 
     def record(self, stream=None):
-        """The recorded sequence (also callable eagerly, capture-safe)."""
+        """The recorded sequence (also callable eagerly, capture-safe).  It
+        starts by clearing the status word, which the capture-safe calls
+        keep raised once an error occurs."""
+        self.plan.clear_status(stream)
         self.plan.symbolic(self.As, self.Bs, capacity=self.capacity, stream=stream,
                            rp=self.row_ptr)
         self.plan.numeric(self.As, self.Bs, self.row_ptr, self.capacity, col=self.col,
@@ -63,21 +66,30 @@ class StageGraph:
 
 
 class MCLGraph:
+    """`iters` MCL iterations on ping-pong buffers, recorded as one graph.
+    `capacity` (entries per buffer) defaults to n * min(topk, n), which
+    always suffices; a smaller one makes an iteration raise SPG_ERR_CAPACITY
+    in the status word, and every later iteration of the replay then skips
+    its work, so result() reports it."""
+
     def __init__(self, X: binding.DeviceCSR, iters: int = 10, r: int = 2,
-                 prune: float = 1e-4, topk: int = 1000, tuning=None):
+                 prune: float = 1e-4, topk: int = 1000, tuning=None,
+                 capacity: int | None = None):
         n = X.shape[0]
         dev = X.row_ptr.device
         self.n, self.iters, self.r, self.prune, self.topk = n, iters, r, prune, topk
         self.plan = binding.Plan(tuning=tuning)
-        cap = n * min(topk, n)
+        cap = n * min(topk, n) if capacity is None else int(capacity)
+        self.capacity = cap
         self.bufs = []
         for _ in range(2):
             self.bufs.append((torch.empty(n + 1, dtype=torch.int32, device=dev),
                               torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
                               torch.empty(max(cap, 1), dtype=torch.float32, device=dev)))
         self.X0 = X
-        # eager warm-up: workspace, kernels
-        binding.mcl_iteration(X, r, prune, topk, plan=self.plan, out=self.bufs[1])
+        # warm-up outside the capture: workspace, kernels
+        binding.mcl_iteration(X, r, prune, topk, plan=self.plan, out=self.bufs[1],
+                              capacity=cap, capture=True)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         self.stream = torch.cuda.Stream()
@@ -89,21 +101,32 @@ class MCLGraph:
         return binding.DeviceCSR((self.n, self.n), rp, col, vals)
 
     def record(self, stream=None):
+        self.plan.clear_status(stream)
         src = self.X0
         for t in range(self.iters):
             dst = self.bufs[t % 2]
             binding.mcl_iteration(src, self.r, self.prune, self.topk, plan=self.plan, out=dst,
-                                  stream=stream, capture=True)
+                                  stream=stream, capture=True, capacity=self.capacity)
             src = self._view(t % 2)
+
+    def buffer(self, t: int) -> binding.DeviceCSR:
+        """Output of iteration t (0-based) after a replay, valid while no
+        later iteration has overwritten its ping-pong buffer (t >= iters - 2).
+        Synchronises; raises if the device status is set."""
+        if not (self.iters - 2 <= t < self.iters):
+            raise ValueError("only the last two iterations' outputs are kept")
+        torch.cuda.synchronize()
+        st = self.plan.status()
+        if st != binding.SPG_OK:
+            raise binding.SpgError(st, "MCLGraph")
+        rp, col, vals = self.bufs[t % 2]
+        nnz = int(rp[-1].item())
+        return binding.DeviceCSR((self.n, self.n), rp, col[:nnz], vals[:nnz])
 
     def replay(self):
         self.graph.replay()
 
     def result(self) -> binding.DeviceCSR:
-        torch.cuda.synchronize()
-        st = self.plan.status()
-        if st != binding.SPG_OK:
-            raise binding.SpgError(st, "MCLGraph")
-        rp, col, vals = self.bufs[(self.iters - 1) % 2]
-        nnz = int(rp[-1].item())
-        return binding.DeviceCSR((self.n, self.n), rp, col[:nnz], vals[:nnz])
+        """Output of the last iteration (synchronises; raises if the device
+        status is set)."""
+        return self.buffer(self.iters - 1)

@@ -25,6 +25,8 @@ __all__ = [
     "HostCSR", "rng_for", "uniform_csr", "varnnz_csr", "rmat_csr",
     "mcl_matrix", "identity_csr", "permutation_csr", "draw_values",
     "column_blocks", "split_inner", "shuffle_rows",
+    "batched_uniform_blocks", "batched_rmat_blocks", "aggregation_csr", "banded_csr",
+    "random_permutation",
 ]
 
 
@@ -253,3 +255,89 @@ def split_inner(A: HostCSR, B: HostCSR, bounds: np.ndarray):
                      B.indices[s:e].copy(), None if B.data is None else B.data[s:e].copy())
         parts.append((Ak, Bk))
     return parts
+
+
+# ---------------------------------------------------------------------------
+# The benchmark workloads' inputs, shared by the benchmark and the full-size
+# parity tests so that both see the same matrices.
+
+WORKLOAD_SEED = 20260321
+
+
+def batched_uniform_blocks(seed: int = WORKLOAD_SEED + 3, m: int = 1 << 18, n: int = 1 << 20,
+                           K: int = 8, kmin: int = 1 << 18, kmax: int = 1 << 20):
+    """Batched stage sequence, uniform variant: K block products A_k B_k
+    with A_k m x K_k and B_k K_k x n, inner sizes K_k ~ U[kmin, kmax], rows of
+    U{4..32} distinct uniform columns, values N(0,1) in FP32."""
+    rng = rng_for(seed, 11)
+    kdims = rng.integers(kmin, kmax + 1, size=K)
+    pairs = []
+    for k in range(K):
+        Ak = varnnz_csr(m, int(kdims[k]), 4, 32, seed, np.float32, "normal", stream=2 * k)
+        Bk = varnnz_csr(int(kdims[k]), n, 4, 32, seed, np.float32, "normal", stream=2 * k + 1)
+        pairs.append((Ak, Bk))
+    return pairs
+
+
+def batched_rmat_blocks(seed: int = WORKLOAD_SEED + 6, scale: int = 20, K: int = 8):
+    """Batched stage sequence, power-law variant: A = R-MAT(0.57, 0.19, 0.19,
+    0.05) of the given scale with edge factor 16, B 2^scale x 2^scale with
+    U{4..32} uniform columns per row (FP32 N(0,1)), split into K contiguous
+    uneven inner blocks.  Returns (A, B, pairs)."""
+    n = 1 << scale
+    A = rmat_csr(scale, 16, seed=seed, dtype=np.float32, values="normal", stream=0)
+    Bm = varnnz_csr(n, n, 4, 32, seed, np.float32, "normal", stream=1)
+    bounds = column_blocks(n, K, n // 16, n // 4, seed)
+    return A, Bm, split_inner(A, Bm, bounds)
+
+
+def aggregation_csr(n: int, nc: int, seed: int, dtype=np.float32, values: str = "one",
+                    stream: int = 0) -> HostCSR:
+    """Rectangular aggregation operator R (n x nc) of an algebraic-multigrid
+    setup: row i holds one entry, in column agg[i], the aggregate of fine
+    point i.  Aggregates are drawn as a random permutation of (i mod nc), so
+    every aggregate gets n/nc points (one more for the first n mod nc)
+    scattered uniformly, as for an unstructured fine matrix.  Values: 'one'
+    (piecewise-constant aggregation) or any kind of draw_values."""
+    if not (1 <= nc <= n):
+        raise ValueError("need 1 <= nc <= n")
+    rng = rng_for(seed, stream)
+    agg = (rng.permutation(n) % nc).astype(np.int32)
+    data = draw_values(rng, n, values, dtype)
+    return HostCSR((n, nc), np.arange(n + 1, dtype=np.int64), agg, data)
+
+
+def banded_csr(n: int, d: int, offsets, halfwidth: int, seed: int, dtype=np.float32,
+               values: str = "u01", stream: int = 0) -> HostCSR:
+    """Structured n x n matrix made of diagonal bands: row i holds d distinct
+    columns drawn uniformly from the union of the windows
+    [i + o - halfwidth, i + o + halfwidth] (clipped to [0, n)) over the band
+    offsets o, so its nonzeros sit on a few diagonals, as in the structured
+    matrices that the paper permutes at random before multiplying."""
+    rng = rng_for(seed, stream)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    w = 2 * halfwidth + 1
+    span = offsets.size * w
+    if d > span:
+        raise ValueError("more entries per row than the bands hold")
+    # d distinct slots of the row's band windows (slot s: band s // w, step s % w)
+    slots = _distinct_rows(rng, n, span, d)
+    cols = np.arange(n)[:, None] + offsets[slots // w] + (slots % w) - halfwidth
+    # clip into [0, n) by reflecting at the edges, then drop repeats
+    cols = np.where(cols < 0, -cols - 1, cols)
+    cols = np.where(cols >= n, 2 * n - 1 - cols, cols)
+    cols = np.sort(cols, axis=1)
+    keep = np.ones_like(cols, dtype=bool)
+    keep[:, 1:] = cols[:, 1:] != cols[:, :-1]
+    lens = keep.sum(axis=1).astype(np.int64)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    indices = cols[keep].astype(np.int32)
+    data = draw_values(rng, indices.size, values, dtype)
+    return HostCSR((n, n), indptr, indices, data)
+
+
+def random_permutation(n: int, seed: int, stream: int = 0) -> np.ndarray:
+    """A uniformly random permutation p of [0, n) (int32): the symmetric
+    permutation maps entry (i, j) to (p[i], p[j])."""
+    return rng_for(seed, stream).permutation(n).astype(np.int32)

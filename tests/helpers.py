@@ -52,10 +52,12 @@ def assert_canonical(M):
 def row_subset(M, rows) -> HostCSR:
     """Rows `rows` of M (in that order) as a new CSR with the same columns."""
     rows = np.asarray(rows, dtype=np.int64)
-    lens = (M.indptr[rows + 1] - M.indptr[rows]).astype(np.int64)
+    indptr = np.asarray(M.indptr, dtype=np.int64)
+    lens = indptr[rows + 1] - indptr[rows]
     ip = np.zeros(rows.size + 1, dtype=np.int64)
     np.cumsum(lens, out=ip[1:])
-    idx = np.concatenate([np.arange(M.indptr[r], M.indptr[r + 1]) for r in rows]) if rows.size else np.zeros(0, np.int64)
+    # entry t of the subset is entry indptr[row] + (t - ip[slot]) of M
+    idx = np.arange(ip[-1], dtype=np.int64) + np.repeat(indptr[rows] - ip[:-1], lens)
     return HostCSR((rows.size, M.shape[1]), ip, M.indices[idx].astype(np.int32),
                    None if M.data is None else M.data[idx])
 

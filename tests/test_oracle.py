@@ -387,3 +387,157 @@ def test_backward_rejects_foreign_pattern():
     C2 = synth.HostCSR(C.shape, C.indptr, (C.indices + 1) % 20, C.data)
     with pytest.raises(oracle.OracleError):
         oracle.backward(A, B, C2, np.ones(C.nnz))
+
+
+# ------------------------------------- §5.7 MCL step in the paper's own order
+def test_mcl_paper_order_hand_worked_golden():
+    g = load_golden("mcl_paper_hand.json")
+    X = csr_from_json(g["X"])
+    for case in g["cases"]:
+        cnt, cols, vals = oracle.mcl_rows(X, np.arange(3), case["r"], case["prune"], case["topk"],
+                                          order="paper")
+        for t, (ecols, evals) in enumerate(case["rows"]):
+            assert cols[t].tolist() == ecols, (case, t)
+            want = [p / q for p, q in evals]
+            assert np.allclose(vals[t], want, rtol=1e-15, atol=0), (case, t)
+
+
+@pytest.mark.parametrize("b", [4, 8, 64])
+def test_mcl_paper_order_block_fixed_point(b):
+    """Blocks of 1/b: the first iteration gives blocks of 1/b^2 (normalised
+    back to 1/b, then squared); from then on E has entries 1/b^3, which
+    normalise to 1/b and square to 1/b^2 again.  Exact for b a power of 2."""
+    nb = 5
+    n = b * nb
+    perm = synth.rng_for(b, 3).permutation(n)
+    rows, cols = [], []
+    for blk in perm.reshape(nb, b):
+        for i in blk:
+            for j in blk:
+                rows.append(i); cols.append(j)
+    rows, cols = np.array(rows), np.array(cols)
+    order = np.lexsort((cols, rows))
+    ip = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=ip[1:])
+    X = synth.HostCSR((n, n), ip, cols[order].astype(np.int32), np.full(n * b, 1.0 / b))
+    Y = X
+    for _ in range(10):
+        Y = oracle.mcl_step(Y, 2, 0.002, 500, order="paper")
+        assert np.array_equal(Y.indptr, X.indptr)
+        assert np.array_equal(Y.indices, X.indices)
+        assert np.all(Y.data == 1.0 / (b * b))
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_mcl_paper_order_no_prune_matches_dense(r):
+    X = synth.mcl_matrix(300, 6, 19, np.float64)
+    Y = oracle.mcl_step(X, r, 0.0, 10 ** 6, order="paper")
+    E = dense(X) @ dense(X)
+    E = (E / E.sum(axis=1, keepdims=True)) ** r
+    assert np.array_equal(mask(Y).astype(bool), E > 0)
+    assert np.allclose(dense(Y), E, rtol=1e-13, atol=0)
+
+
+def test_mcl_paper_order_prune_keeps_the_large_entries():
+    """With the paper's threshold 0.002: kept entries are exactly those whose
+    normalised expansion value is >= 0.002 (dense check), at most 500 per
+    row, each output is that value squared, and no row is empty."""
+    X = synth.mcl_matrix(600, 40, 23, np.float64)
+    Y = oracle.mcl_step(X, 2, 0.002, 500, order="paper")
+    E = dense(X) @ dense(X)
+    N = E / E.sum(axis=1, keepdims=True)
+    keep = N >= 0.002
+    empty = ~keep.any(axis=1)
+    keep[empty, np.argmax(N[empty], axis=1)] = True
+    assert np.array_equal(mask(Y).astype(bool), keep)
+    assert np.allclose(dense(Y)[keep], N[keep] ** 2, rtol=1e-13, atol=0)
+    lens = np.diff(Y.indptr)
+    assert lens.max() <= 500 and lens.min() >= 1
+    assert_canonical(Y)
+
+
+# ------------------------------------- §5.3 random permutation preprocessing
+def test_permute_identity_and_inverse():
+    A = synth.shuffle_rows(synth.varnnz_csr(300, 250, 0, 30, 4, np.float64, "normal"), 4)
+    I = oracle.permute(A)
+    rid = np.repeat(np.arange(300), np.diff(A.indptr))
+    order = np.lexsort((A.indices, rid))  # A with every row sorted (numpy, not the oracle)
+    ref = synth.HostCSR(A.shape, A.indptr, A.indices[order], A.data[order])
+    assert np.array_equal(I.indptr, ref.indptr) and np.array_equal(I.indices, ref.indices)
+    assert np.array_equal(I.data, ref.data)
+    p, q = synth.random_permutation(300, 1), synth.random_permutation(250, 2)
+    Bp = oracle.permute(A, p, q)
+    back = oracle.permute(synth.HostCSR(Bp.shape, Bp.indptr, Bp.indices, Bp.data),
+                          np.argsort(p).astype(np.int32), np.argsort(q).astype(np.int32))
+    assert np.array_equal(back.indptr, ref.indptr) and np.array_equal(back.indices, ref.indices)
+    assert np.array_equal(back.data, ref.data)
+
+
+def test_permute_matches_dense_permutation_matrices():
+    A = synth.varnnz_csr(120, 90, 0, 20, 5, np.float64, "normal")
+    p, q = synth.random_permutation(120, 3), synth.random_permutation(90, 4)
+    Bp = oracle.permute(A, p, q)
+    Pr = np.zeros((120, 120)); Pr[p, np.arange(120)] = 1.0
+    Pc = np.zeros((90, 90)); Pc[q, np.arange(90)] = 1.0
+    assert np.array_equal(dense(Bp), Pr @ dense(A) @ Pc.T)
+    assert np.array_equal(mask(Bp), (Pr @ mask(A) @ Pc.T).astype(np.int64))
+    assert_canonical(Bp)
+
+
+def test_symmetric_permutation_commutes_with_squaring():
+    A = synth.banded_csr(400, 6, [0, 100, -100], 5, 6, np.float64, "int")
+    p = synth.random_permutation(400, 5)
+    PA = oracle.permute(A, p, p)
+    PAh = synth.HostCSR(PA.shape, PA.indptr, PA.indices, PA.data)
+    lhs = oracle.spgemm(PAh, PAh)
+    rhs = oracle.permute(oracle.spgemm(A, A), p, p)
+    assert np.array_equal(lhs.indptr, rhs.indptr) and np.array_equal(lhs.indices, rhs.indices)
+    assert np.array_equal(lhs.data, rhs.data)  # small integers: exact
+
+
+def test_permute_rejects_non_permutations():
+    A = synth.varnnz_csr(10, 10, 1, 3, 6, np.float64, "normal")
+    bad = np.arange(10, dtype=np.int32)
+    bad[3] = 4
+    with pytest.raises(oracle.OracleError):
+        oracle.permute(A, bad, None)
+    with pytest.raises(oracle.OracleError):
+        oracle.permute(A, None, np.arange(1, 11, dtype=np.int32))
+
+
+def test_banded_generator_has_bands():
+    A = synth.banded_csr(5000, 12, [0, 1000, -1000], 20, 7, np.float32)
+    rid = np.repeat(np.arange(5000), np.diff(A.indptr))
+    off = A.indices.astype(np.int64) - rid
+    near = np.min(np.abs(off[:, None] - np.array([0, 1000, -1000])[None, :]), axis=1)
+    inner = (rid >= 1100) & (rid < 3900)  # rows whose windows stay inside [0, n)
+    assert np.all(near[inner] <= 20)
+    assert_canonical(A)
+
+
+# ------------------------------- §5.4 restriction operator product C = A R
+@pytest.mark.parametrize("values", ["one", "int"])
+def test_restriction_product_is_a_row_merge_by_aggregate(values):
+    """R has one entry per row (fine point k -> aggregate agg[k], weight
+    w_k), so row i of C = A R holds, for every aggregate j reached from A_i,
+    the sum of a_ik w_k over the k of A_i in aggregate j.  Built here by a
+    segmented sum in numpy, independently of the oracle's product."""
+    m, n, nc = 700, 900, 111
+    A = synth.varnnz_csr(m, n, 0, 25, 31, np.float64, "int")
+    R = synth.aggregation_csr(n, nc, 31, np.float64, values)
+    assert np.all(np.diff(R.indptr) == 1) and np.bincount(R.indices, minlength=nc).min() >= n // nc
+    C = oracle.spgemm(A, R)
+    rid = np.repeat(np.arange(m), np.diff(A.indptr))
+    agg = R.indices[A.indices]
+    contrib = A.data * R.data[A.indices]
+    order = np.lexsort((agg, rid))
+    rid, agg, contrib = rid[order], agg[order], contrib[order]
+    first = np.ones(rid.size, dtype=bool)
+    first[1:] = (rid[1:] != rid[:-1]) | (agg[1:] != agg[:-1])
+    starts = np.nonzero(first)[0]
+    sums = np.add.reduceat(contrib, starts) if starts.size else np.zeros(0)
+    ip = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rid[starts], minlength=m), out=ip[1:])
+    assert np.array_equal(C.indptr, ip)
+    assert np.array_equal(C.indices, agg[starts])
+    assert np.array_equal(C.data, sums)  # small integers: exact in any order

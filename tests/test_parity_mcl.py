@@ -9,6 +9,7 @@ import pytest
 import oracle
 from paper_2603_21444_amd import synth
 from helpers import csr_from_json, load_golden, row_ids
+from mcl_check import check_mcl_step
 
 pytestmark = pytest.mark.gpu
 
@@ -23,33 +24,7 @@ def B():
 
 
 def _check_step(X, got, r, prune, topk, rows=None):
-    """Compare the GPU output rows with the oracle on the same input X."""
-    n = X.shape[0]
-    rows = np.arange(n) if rows is None else np.asarray(rows)
-    Xf = X.with_data(X.data.astype(np.float64))
-    cnt, cols, vals = oracle.mcl_rows(Xf, rows, r, prune, topk)
-    # pre-prune normalised values for the band rule
-    _, allc, allv = oracle.mcl_rows(Xf, rows, r, 0.0, 10 ** 9)
-    nflip = 0
-    for t, i in enumerate(rows):
-        s, e = int(got.indptr[i]), int(got.indptr[i + 1])
-        gc, gv = got.indices[s:e], got.data[s:e].astype(np.float64)
-        assert np.all(np.diff(gc) > 0), f"row {i} not canonical"
-        oc, ov = cols[t], vals[t]
-        if np.array_equal(gc, oc):
-            assert np.allclose(gv, ov, rtol=1e-4, atol=0), f"row {i} values"
-            continue
-        # pattern differs: every differing column must sit in the band
-        pre = dict(zip(allc[t].tolist(), allv[t].tolist()))
-        ranked = np.sort(allv[t])[::-1]
-        kth = ranked[min(topk, ranked.size) - 1] if ranked.size else 0.0
-        for j in set(gc.tolist()) ^ set(oc.tolist()):
-            v = pre[j]
-            near_prune = abs(v - prune) <= 1e-4 * prune
-            near_kth = abs(v - kth) <= 1e-4 * kth
-            assert near_prune or near_kth, f"row {i} col {j}: value {v} outside the band"
-            nflip += 1
-    return nflip
+    return check_mcl_step(X, got, r, prune, topk, rows)
 
 
 def test_hand_worked_golden(B):

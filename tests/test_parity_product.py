@@ -228,32 +228,12 @@ def test_capacity_mode_reports_too_small_output(B):
 @pytest.mark.slow
 def test_uniform_2p20_fp32_full_size(B):
     """One GPU's block share: A, B independent 2^20 x 2^20, 16 uniform columns
-    per row, FP32 in (0,1].  row_ptr checked in full against the oracle's
-    count; col_idx and values on 4096 sampled rows; row sums of C against
-    A (B 1) on every row."""
+    per row, FP32 in (0,1] (the benchmark's plain workload, same seed):
+    row_ptr and col_idx bit-exact on every row, every value within
+    1e-5 * sum |a||b| of the FP64 oracle's."""
     n = 1 << 20
     A = synth.uniform_csr(n, n, 16, SEED + 1, np.float32, "u01", stream=0)
     Bm = synth.uniform_csr(n, n, 16, SEED + 1, np.float32, "u01", stream=1)
     got = gpu_product(B, A, Bm, np.float32)
-    Af = A.astype(np.float64)
-    Bf = Bm.astype(np.float64)
-    ref_rp = np.zeros(n + 1, dtype=np.int64)
-    import ctypes as C
-    L = oracle.lib()
-    rc = L.oracle_spgemm_count(C.c_int64(n), C.c_int64(n), C.c_int64(n),
-                               Af.indptr.ctypes.data_as(C.c_void_p), Af.indices.ctypes.data_as(C.c_void_p),
-                               Bf.indptr.ctypes.data_as(C.c_void_p), Bf.indices.ctypes.data_as(C.c_void_p),
-                               ref_rp.ctypes.data_as(C.c_void_p))
-    assert rc == 0
-    assert np.array_equal(got.indptr.astype(np.int64), ref_rp)
-    rows = np.sort(synth.rng_for(SEED, 5).choice(n, 4096, replace=False))
-    rows = np.concatenate([[0, n - 1], rows])
-    ref, S = oracle.spgemm(row_subset(Af, rows), Bf, with_abs=True)
-    sub = row_subset(got, rows)
-    assert_same_csr(sub, ref, S, np.float32, what="2^20 sampled rows")
-    # every row: sum_j C_ij = sum_k a_ik (sum_j b_kj)
-    rid = np.repeat(np.arange(n), np.diff(got.indptr))
-    lhs = np.bincount(rid, weights=got.data.astype(np.float64), minlength=n)
-    bsum = np.bincount(np.repeat(np.arange(n), np.diff(Bf.indptr)), weights=Bf.data, minlength=n)
-    rhs = np.bincount(np.repeat(np.arange(n), np.diff(Af.indptr)), weights=Af.data * bsum[Af.indices], minlength=n)
-    assert np.all(np.abs(lhs - rhs) <= 1e-5 * rhs + 1e-30)
+    ref, S = oracle.spgemm(A.astype(np.float64), Bm.astype(np.float64), with_abs=True)
+    assert_same_csr(got, ref, S, np.float32, what="2^20 uniform, every row")
