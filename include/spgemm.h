@@ -49,7 +49,8 @@ typedef enum {
   SPG_ERR_WORKSPACE = 5,   /* workspace missing or too small */
   SPG_ERR_HIP = 6,         /* a HIP runtime call failed */
   SPG_ERR_UNSUPPORTED = 7, /* argument combination not supported */
-  SPG_ERR_ARG = 8          /* NULL pointer or out-of-range scalar argument */
+  SPG_ERR_ARG = 8,         /* NULL pointer or out-of-range scalar argument */
+  SPG_ERR_SCRATCH = 9      /* too large for the library's static scratch (no-allocation call) */
 } spg_status;
 
 typedef enum { SPG_F32 = 0, SPG_F64 = 1 } spg_dtype;
@@ -143,6 +144,35 @@ int spgemm_plan_bins(spg_plan plan, int32_t *sym_counts, int32_t *num_counts);
 int spgemm_symbolic(spg_plan plan, int32_t K, const spg_csr *A, const spg_csr *B,
                     int32_t *C_row_ptr, int64_t *C_nnz_host, int64_t capacity,
                     void *workspace, size_t ws_bytes, void *stream);
+
+/* Symbolic pass that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It is spgemm_symbolic in capture-safe
+ * mode (nothing is read back; nnz(C) > capacity raises SPG_ERR_CAPACITY in
+ * the device status word) whose workspace is a static device array inside
+ * the library, SPG_SCRATCH_BYTES per device, instead of a caller argument.
+ * The caller still passes the operands, C_row_ptr [m+1] and, afterwards,
+ * C_col_idx / C_vals [capacity] to spgemm_numeric on the same plan (which
+ * then also works in that array).  The library takes the array's device
+ * address once per device, on that device's first call.
+ *  - Limit: a problem whose workspace (spgemm_workspace_size with fewer
+ *    concurrent heavy rows, at least one) exceeds SPG_SCRATCH_BYTES returns
+ *    SPG_ERR_SCRATCH before any work is queued; about 9 m + 8 n bytes with
+ *    one heavy row, so m = n = 2^22 is beyond it.
+ *  - Sharing: every such call on a device uses that device's one array and
+ *    leaves its contents behind (the kernels clear what they need).  Calls
+ *    that overlap on one device race, including a symbolic call of one plan
+ *    between the symbolic and numeric calls of another: serialise them (one
+ *    stream, or events).
+ *  - Status: as for other capture-safe calls, the status word (in the
+ *    array) is cleared on a plan's first use of the array and is sticky
+ *    afterwards; spgemm_plan_clear_status clears it, spgemm_plan_status
+ *    reads it.
+ * Errors: as spgemm_symbolic, plus SPG_ERR_SCRATCH, and SPG_ERR_HIP if the
+ * array's device address cannot be obtained. */
+#define SPG_SCRATCH_BYTES (128u << 20)
+int spgemm_symbolic_noalloc(spg_plan plan, int32_t K, const spg_csr *A, const spg_csr *B,
+                            int32_t *C_row_ptr, int64_t capacity, void *stream);
 
 /* Numeric pass: values and canonical column order of C, for the same K
  * operand patterns as the plan's symbolic call (values may differ: the plan

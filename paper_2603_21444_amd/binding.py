@@ -23,6 +23,8 @@ LIB_PATH = os.environ.get("SPG_LIB_PATH", os.path.join(HERE, "libspgemm.so"))
 
 SPG_OK, SPG_ERR_INVALID, SPG_ERR_SHAPE, SPG_ERR_OVERFLOW = 0, 1, 2, 3
 SPG_ERR_CAPACITY, SPG_ERR_WORKSPACE, SPG_ERR_HIP, SPG_ERR_UNSUPPORTED, SPG_ERR_ARG = 4, 5, 6, 7, 8
+SPG_ERR_SCRATCH = 9
+SPG_SCRATCH_BYTES = 128 << 20
 SPG_F32, SPG_F64 = 0, 1
 SPG_FLAG_VALIDATE = 1
 SPG_MAX_PARTS = 16
@@ -32,7 +34,7 @@ SPG_NBINS = 16
 EXPORTS = [
     "spgemm_plan_create", "spgemm_plan_destroy", "spgemm_workspace_size",
     "spgemm_plan_status", "spgemm_plan_clear_status", "spgemm_plan_info", "spgemm_status_string",
-    "spgemm_symbolic", "spgemm_numeric", "spgemm_merge", "spgemm_backward",
+    "spgemm_symbolic", "spgemm_symbolic_noalloc", "spgemm_numeric", "spgemm_merge", "spgemm_backward",
     "spgemm_mcl_workspace_size", "spgemm_mcl_iteration",
     "spgemm_permute_workspace_size", "spgemm_permute",
     "spgemm_default_tuning", "spgemm_plan_set_tuning", "spgemm_plan_bins",
@@ -78,6 +80,7 @@ def lib():
             "spgemm_plan_info": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64)]),
             "spgemm_status_string": (C.c_char_p, [C.c_int]),
             "spgemm_symbolic": (C.c_int, [P, I32, PC, PC, P, C.POINTER(I64), I64, P, C.c_size_t, P]),
+            "spgemm_symbolic_noalloc": (C.c_int, [P, I32, PC, PC, P, I64, P]),
             "spgemm_numeric": (C.c_int, [P, I32, PC, PC, C.c_int, P, P, P]),
             "spgemm_merge": (C.c_int, [P, I32, PC, C.c_int, P, C.POINTER(I64), I64, P, P, P,
                                        C.c_size_t, P]),
@@ -262,6 +265,14 @@ class Plan:
                                      -1 if eager else int(capacity), _ptr(ws), ws.numel(),
                                      _stream(stream)), "spgemm_symbolic")
         return rp, (int(nnz.value) if eager else None)
+
+    def symbolic_noalloc(self, As, Bs, rp, capacity: int, stream=None):
+        """Symbolic pass in the library's static scratch (no workspace, no
+        read-back; errors go to the device status word)."""
+        _check(lib().spgemm_symbolic_noalloc(self.h, len(As), _arr(As), _arr(Bs), _ptr(rp),
+                                             int(capacity), _stream(stream)),
+               "spgemm_symbolic_noalloc")
+        return rp
 
     def numeric(self, As, Bs, rp, nnz: int, dtype=None, col=None, vals=None, stream=None):
         torch = _torch()

@@ -433,6 +433,7 @@ const char *spgemm_status_string(int status) {
     case SPG_ERR_HIP: return "HIP runtime error";
     case SPG_ERR_UNSUPPORTED: return "unsupported argument combination";
     case SPG_ERR_ARG: return "bad argument";
+    case SPG_ERR_SCRATCH: return "problem too large for the library's static scratch buffer";
     default: return "unknown status";
   }
 }
@@ -471,6 +472,67 @@ int spgemm_symbolic(spg_plan plan, int32_t K, const spg_csr *A, const spg_csr *B
   plan->merge_mode = false;
   rc = run_symbolic(plan, pr, A, B, C_row_ptr, C_nnz_host, capacity, workspace, ws_bytes,
                     static_cast<hipStream_t>(stream));
+  if (rc == SPG_OK) remember_operands(plan, K, A, B);
+  return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Static scratch for spgemm_symbolic_noalloc: one array per device, held by
+// the device until the process ends.  In host code `scratch` names a host
+// stand-in, never the device memory: host code only ever uses the address
+// that hipGetSymbolAddress returns for the current device (g_scratch_ptr).
+namespace {
+
+__device__ __align__(256) char scratch[SPG_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+int g_scratch_dev[kMaxDevices];
+char *g_scratch_ptr[kMaxDevices];
+int g_nscratch = 0;
+
+// Device address of this device's scratch (looked up once per device, with
+// the device current); nullptr if the lookup fails.
+char *scratch_for_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  for (int t = 0; t < g_nscratch; ++t)
+    if (g_scratch_dev[t] == dev) return g_scratch_ptr[t];
+  if (g_nscratch == kMaxDevices) return nullptr;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  g_scratch_dev[g_nscratch] = dev;
+  g_scratch_ptr[g_nscratch] = static_cast<char *>(ptr);
+  return g_scratch_ptr[g_nscratch++];
+}
+
+}  // namespace
+
+extern "C" {
+
+int spgemm_symbolic_noalloc(spg_plan plan, int32_t K, const spg_csr *A, const spg_csr *B,
+                            int32_t *C_row_ptr, int64_t capacity, void *stream) {
+  if (!plan || !C_row_ptr || capacity < 0) return SPG_ERR_ARG;
+  Problem pr;
+  int rc = fill_parts(pr, K, A, B, false);
+  if (rc) return rc;
+  // as many concurrent heavy rows as the scratch holds, at most the usual
+  // number (at least one)
+  const int want = plan->tun.heavy_slots > 0 ? plan->tun.heavy_slots : default_heavy_slots(pr.n);
+  int heavy = want;
+  while (heavy > 1 && ws_layout(pr.m, pr.n, heavy).total > (size_t)SPG_SCRATCH_BYTES) heavy /= 2;
+  if (ws_layout(pr.m, pr.n, heavy).total > (size_t)SPG_SCRATCH_BYTES) return SPG_ERR_SCRATCH;
+  (void)dev_info();  // per-device set-up (kernel attributes) before the first launch
+  char *ws = scratch_for_current_device();
+  if (!ws) return SPG_ERR_HIP;
+  plan->merge_mode = false;
+  rc = run_symbolic(plan, pr, A, B, C_row_ptr, nullptr, capacity, ws,
+                    (size_t)SPG_SCRATCH_BYTES, static_cast<hipStream_t>(stream), heavy);
   if (rc == SPG_OK) remember_operands(plan, K, A, B);
   return rc;
 }
