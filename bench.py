@@ -10,13 +10,22 @@ inputs resident in HBM.  Prints one JSON line.
   roofline   numeric pass: algorithmic bytes (read A, B, C.row_ptr; write
              C) over its average duration, timed with HIP events on the
              stream it runs on, against 8 TB/s
-  cpu_baseline  the FP64 oracle on the host cores, same inputs
+  cpu_baseline  the FP64 oracle on the host cores, same inputs (all
+             threads on the whole product; one thread on a row sample)
 
-Also reported (unless --only-plain): the batched stage sequence (8 uneven
-block products summed into one C; per-block eager launches + sparse sum vs
-the fused product captured as one graph), uniform and R-MAT variants, and
-the backward pass at fixed sparsity; with --mcl, 10 Markov-clustering
-iterations in one graph.
+Further legs, each with its own workload, all on by default (--legs picks
+some):
+  batched      8 uneven block products summed into one C: per-block eager
+               launches + sparse sum, the fused product eagerly, and the
+               fused product captured as one graph (autotuned)
+  rmat         the same with a power-law (R-MAT scale 20) left operand
+  backward     dA, dB at fixed sparsity
+  mcl          10 Markov-clustering iterations (n = 2^19) in one graph, and
+               the same iterations eagerly with per-iteration timing
+  mcl_paper    the same in the paper's step order (prune 0.002, squaring)
+  restriction  C = A R with an aggregation operator R (2^20 x 2^17)
+  permute      random symmetric permutation of a banded matrix, and A^2 of
+               the banded matrix against A^2 of the permuted one
 """
 from __future__ import annotations
 
@@ -34,6 +43,7 @@ sys.path.insert(0, ROOT)
 METRIC = "SpGEMM GFLOP/s + HBM GB/s (% peak): plain vs batched-graph vs backward"
 HBM_PEAK_GBS = 8000.0
 SEED = 20260321
+LEGS = ["batched", "rmat", "backward", "mcl", "mcl_paper", "restriction", "permute"]
 
 
 def log(msg):
@@ -51,11 +61,22 @@ def make_inputs(n, d, seed):
     return A, B
 
 
-def bench_plain(args, A, B):
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def _roof(alg_bytes, ms):
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    return round(gbs, 1), round(gbs / HBM_PEAK_GBS, 4)
+
+
+def time_product(args, dA, dB, plan=None):
+    """Symbolic + numeric per step (wall clock, eager read-back of nnz) and
+    the numeric pass alone (HIP events on the stream it runs on)."""
     import torch
     from paper_2603_21444_amd import binding
-    dA, dB = binding.to_device(A), binding.to_device(B)
-    plan = binding.Plan()
+    plan = plan or binding.Plan()
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
@@ -80,11 +101,24 @@ def bench_plain(args, A, B):
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     num_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    nnz_c, products = plan.info()
+    _, products = plan.info()
     return dict(ms_step=ms_step, num_ms=num_ms, nnz=nnz, products=products)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A, B, budget_s):
+    """The oracle as it stands: all threads on the whole product (mean of up
+    to 6 runs within the budget), one thread on the first 2^16 rows."""
     import oracle
     Af, Bf = A.astype(np.float64), B.astype(np.float64)
     oracle.spgemm(oracle_sample(Af, 1024), Bf)  # warm the library and caches
@@ -97,10 +131,24 @@ def cpu_baseline(A, B, budget_s):
         runs += 1
         del C
     sec = t_total / runs
+    threads = oracle.num_threads()
+    rows1 = min(1 << 16, A.shape[0])
+    As = oracle_sample(Af, rows1)
+    p1 = int(oracle.rowub(As, Bf).sum())
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.spgemm(As, Bf)
+        sec1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
     return dict(value=round(2.0 * total_products / sec / 1e9, 3), unit="GFLOP/s",
-                cores=oracle.num_threads(), kind="oracle",
-                sample=f"full C = A B (2^20 rows, {total_products} products), mean of {runs} run(s), "
-                       f"{sec:.2f} s each")
+                cores=threads, kind="oracle",
+                sample=f"full C = A B (2^20 rows, {total_products} products), {threads} threads, "
+                       f"mean of {runs} run(s), {sec:.2f} s each; one thread: first {rows1} rows "
+                       f"({p1} products) in {sec1:.2f} s",
+                single_thread_value=round(2.0 * p1 / sec1 / 1e9, 4),
+                cpu_model=cpu_model(), host_cpus=os.cpu_count())
 
 
 def oracle_sample(M, rows):
@@ -109,71 +157,88 @@ def oracle_sample(M, rows):
     return HostCSR((rows, M.shape[1]), M.indptr[:rows + 1], M.indices[:e], M.data[:e])
 
 
-def _events(n):
+def _wall(fn, reps):
     import torch
-    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps, out
 
 
 def _time_batched(args, pairs, m, bytes_in):
-    """Per-block eager launches (symbolic with read-back + numeric per block,
-    then the sparse sum) against the fused product captured as one graph."""
+    """Three forms of the same sum of block products on the same GPU:
+      per-block eager: per block an eager product (symbolic with nnz read-
+        back, numeric) on its own reused plan and workspace, then the sparse
+        sum of the partials on a reused plan;
+      fused eager: the fused product's capture-safe calls issued eagerly;
+      graph: the same calls captured once and replayed.
+    The graph uses the autotuner's tuning for this input."""
     import torch
-    from paper_2603_21444_amd import binding
+    from paper_2603_21444_amd import autotune, binding
     from paper_2603_21444_amd.graph import StageGraph
 
-    def eager():
-        parts = [binding.spgemm(a, b) for a, b in pairs]
-        return binding.merge(parts)
+    plans = [binding.Plan() for _ in pairs]
+    mplan = binding.Plan()
+
+    def per_block():
+        parts = [binding.spgemm(a, b, plan=p) for (a, b), p in zip(pairs, plans)]
+        return binding.merge(parts, plan=mplan)
 
     for _ in range(max(1, args.warmup)):
-        Ce = eager()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        Ce = eager()
-    torch.cuda.synchronize()
-    eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        Ce = per_block()
     nnz = Ce.nnz
     del Ce
+    per_block_ms, Ce = _wall(per_block, args.steps)
+    del Ce
+    del plans, mplan
     torch.cuda.empty_cache()
-    g = StageGraph(pairs)
+    As = [a for a, _ in pairs]
+    Bs = [b for _, b in pairs]
+    t0 = time.perf_counter()
+    tuning = autotune.tune(As, Bs, use_cache=False)
+    tune_s = time.perf_counter() - t0
+    g = StageGraph(pairs, tuning=tuning)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, args.warmup)):
+        g.record(stream)
+    fused_ms, _ = _wall(lambda: g.record(stream), args.steps)
     for _ in range(max(1, args.warmup)):
         g.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.replay()
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    graph_ms, _ = _wall(g.replay, args.steps)
     Cg = g.result()
     assert Cg.nnz == nnz, (Cg.nnz, nnz)
-    plan = binding.Plan()
-    plan.symbolic([a for a, _ in pairs], [b for _, b in pairs])
-    _, products = plan.info()
+    _, products = g.plan.info()
+    if products < 0:
+        plan = binding.Plan()
+        plan.symbolic(As, Bs)
+        _, products = plan.info()
     del g, Cg
     torch.cuda.empty_cache()
     alg = bytes_in + 4 * (m + 1) + 8 * nnz
+    gbs, frac = _roof(alg, graph_ms)
     return {
         "products": int(products), "nnz_C": int(nnz),
-        "graph_ms": round(graph_ms, 3), "eager_per_block_ms": round(eager_ms, 3),
+        "graph_ms": round(graph_ms, 3), "eager_fused_ms": round(fused_ms, 3),
+        "eager_per_block_ms": round(per_block_ms, 3),
         "graph_gflops": round(2 * products / graph_ms / 1e6, 2),
-        "eager_gflops": round(2 * products / eager_ms / 1e6, 2),
-        "graph_speedup": round(eager_ms / graph_ms, 3),
-        "graph_alg_GBs": round(alg / graph_ms / 1e6, 1),
+        "eager_fused_gflops": round(2 * products / fused_ms / 1e6, 2),
+        "eager_gflops": round(2 * products / per_block_ms / 1e6, 2),
+        "graph_speedup": round(per_block_ms / graph_ms, 3),
+        "fusion_speedup": round(per_block_ms / fused_ms, 3),
+        "capture_speedup": round(fused_ms / graph_ms, 3),
+        "graph_alg_GBs": gbs, "graph_hbm_frac": frac, "algorithmic_bytes": int(alg),
+        "tuning": autotune.describe(tuning), "tune_s": round(tune_s, 2),
     }
 
 
 def bench_batched(args):
     """8 uneven block products summed into one C (uniform variant)."""
     from paper_2603_21444_amd import binding, synth
-    m, n, K = 1 << 18, 1 << 20, 8
-    rng = synth.rng_for(SEED + 3, 11)
-    kdims = rng.integers(1 << 18, (1 << 20) + 1, size=K)
-    pairs = []
-    for k in range(K):
-        Ak = synth.varnnz_csr(m, int(kdims[k]), 4, 32, SEED + 3, np.float32, "normal", stream=2 * k)
-        Bk = synth.varnnz_csr(int(kdims[k]), n, 4, 32, SEED + 3, np.float32, "normal", stream=2 * k + 1)
-        pairs.append((binding.to_device(Ak), binding.to_device(Bk)))
+    m = 1 << 18
+    pairs = [(binding.to_device(a), binding.to_device(b))
+             for a, b in synth.batched_uniform_blocks(SEED + 3)]
     log("[bench] batched blocks generated")
     bytes_in = sum(csr_bytes(a.shape[0], a.nnz, 4) + csr_bytes(b.shape[0], b.nnz, 4) for a, b in pairs)
     r = _time_batched(args, pairs, m, bytes_in)
@@ -187,11 +252,8 @@ def bench_batched_rmat(args):
     uneven inner blocks; B 2^20 x 2^20 with 4..32 uniform columns per row."""
     from paper_2603_21444_amd import binding, synth
     n = 1 << 20
-    seed = SEED + 6
-    A = synth.rmat_csr(20, 16, seed=seed, dtype=np.float32, values="normal", stream=0)
-    Bm = synth.varnnz_csr(n, n, 4, 32, seed, np.float32, "normal", stream=1)
-    bounds = synth.column_blocks(n, 8, n // 16, n // 4, seed)
-    pairs = [(binding.to_device(a), binding.to_device(b)) for a, b in synth.split_inner(A, Bm, bounds)]
+    _, _, hpairs = synth.batched_rmat_blocks(SEED + 6)
+    pairs = [(binding.to_device(a), binding.to_device(b)) for a, b in hpairs]
     log("[bench] R-MAT blocks generated")
     bytes_in = sum(csr_bytes(a.shape[0], a.nnz, 4) + csr_bytes(b.shape[0], b.nnz, 4) for a, b in pairs)
     r = _time_batched(args, pairs, n, bytes_in)
@@ -227,33 +289,118 @@ def bench_backward(args):
     ms = ev[0].elapsed_time(ev[1]) / args.steps
     _, products = plan.info()
     alg = csr_bytes(n, A.nnz, 4) + csr_bytes(n, B.nnz, 4) + 4 * (n + 1) + 8 * nnz + 4 * (A.nnz + B.nnz)
+    gbs, frac = _roof(alg, ms)
     return {
         "workload": "dA = (W B^T) on S(A), dB = (A^T W) on S(B); A, B 2^18 x 2^18, 16 nnz/row, FP32",
         "products": int(products), "ms": round(ms, 4),
         "gflops": round(4 * products / ms / 1e6, 2),
-        "alg_GBs": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+        "alg_GBs": gbs, "hbm_frac": frac, "algorithmic_bytes": int(alg),
     }
 
 
-def bench_mcl(args):
-    """10 Markov-clustering iterations on n = 2^19 (24 + 1 per column), FP32,
-    recorded as one graph."""
+def bench_mcl(args, order="workload"):
+    """10 Markov-clustering iterations on n = 2^19 (24 + 1 per column), FP32:
+    eagerly, one at a time with HIP events around each (products from the
+    plan), then recorded as one graph and replayed."""
     import torch
     from paper_2603_21444_amd import binding, synth
     from paper_2603_21444_amd.graph import MCLGraph
     n = 1 << 19
+    if order == "workload":
+        r, prune, topk = 2, 1e-4, 1000
+    else:
+        r, prune, topk = 2, 0.002, 500
     X = synth.mcl_matrix(n, 24, SEED + 4, np.float32)
-    g = MCLGraph(binding.to_device(X), iters=10)
+    dX = binding.to_device(X)
+    plan = binding.Plan()
+    s = torch.cuda.current_stream()
+    Y = binding.mcl_iteration(dX, r, prune, topk, plan=plan, order=order)  # warm-up
+    del Y
+    torch.cuda.synchronize()
+    per_it = []
+    Y = dX
+    for t in range(10):
+        nnz_in = Y.nnz
+        e0, e1 = _events(2)
+        e0.record(s)
+        Y = binding.mcl_iteration(Y, r, prune, topk, plan=plan, order=order)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        _, products = plan.info()
+        alg = csr_bytes(n, nnz_in, 4) + csr_bytes(n, Y.nnz, 4)
+        per_it.append({"ms": round(ms, 2), "products": int(products), "nnz_out": int(Y.nnz),
+                       "gflops": round(2 * products / ms / 1e6, 1),
+                       "alg_GBs": round(alg / ms / 1e6, 1)})
+    eager_ms = sum(p["ms"] for p in per_it)
+    total_products = sum(p["products"] for p in per_it)
+    del Y
+    torch.cuda.empty_cache()
+    g = MCLGraph(dX, iters=10, r=r, prune=prune, topk=topk, order=order)
     g.replay()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.replay()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
-    Y = g.result()
-    return {"workload": "MCL, n = 2^19, 24 + 1 nnz per column, r = 2, prune < 1e-4, top-1000, "
-                        "10 iterations in one graph",
-            "ms_10_iterations": round(ms, 2), "final_nnz": Y.nnz}
+    reps = 1
+    graph_ms, _ = _wall(g.replay, reps)
+    Yg = g.result()
+    out = {"workload": (f"MCL ({'inflate r=2, renormalise, prune < 1e-4, top-1000' if order == 'workload' else 'paper order: normalise, prune < 0.002, square'}), "
+                        "n = 2^19, 24 + 1 nnz per column, FP32, 10 iterations in one graph"),
+           "ms_10_iterations_graph": round(graph_ms, 2), "ms_10_iterations_eager": round(eager_ms, 2),
+           "products_10_iterations": int(total_products),
+           "graph_gflops": round(2 * total_products / graph_ms / 1e6, 1),
+           "final_nnz": Yg.nnz, "per_iteration_eager": per_it}
+    del g, Yg
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_restriction(args, A):
+    """C = A R: A the plain workload's left operand (2^20 x 2^20, 16 per
+    row), R an aggregation operator 2^20 x 2^17 (one entry per row, FP32 in
+    (0,1]): 16 products per row, the low-flop regime."""
+    from paper_2603_21444_amd import binding, synth
+    n, nc = A.shape[0], A.shape[0] >> 3
+    R = synth.aggregation_csr(n, nc, SEED + 7, np.float32, "u01")
+    dA, dR = binding.to_device(A), binding.to_device(R)
+    r = time_product(args, dA, dR)
+    alg = csr_bytes(n, A.nnz, 4) + csr_bytes(n, R.nnz, 4) + 4 * (n + 1) + 8 * r["nnz"]
+    gbs, frac = _roof(alg, r["num_ms"])
+    return {"workload": "C = A R, A 2^20 x 2^20 uniform 16/row FP32 (0,1], R 2^20 x 2^17 aggregation "
+                        "(one entry per row, aggregates of 8 points, FP32 (0,1])",
+            "products": int(r["products"]), "nnz_C": int(r["nnz"]),
+            "ms_step": round(r["ms_step"], 4), "numeric_ms": round(r["num_ms"], 4),
+            "gflops": round(2 * r["products"] / r["ms_step"] / 1e6, 2),
+            "numeric_alg_GBs": gbs, "numeric_hbm_frac": frac, "algorithmic_bytes": int(alg)}
+
+
+def bench_permute(args):
+    """Random symmetric permutation of a banded 2^20 x 2^20 matrix (16 per
+    row on three diagonal bands), timed on the device, and C = A A on the
+    banded matrix against C = A A on the permuted one."""
+    import torch
+    from paper_2603_21444_amd import binding, synth
+    n = 1 << 20
+    A = synth.banded_csr(n, 16, [0, n // 8, -n // 8], 256, SEED + 8, np.float32)
+    p = torch.from_numpy(synth.random_permutation(n, SEED + 8)).cuda()
+    dA = binding.to_device(A)
+    plan = binding.Plan()
+    out = (torch.empty(n + 1, dtype=torch.int32, device="cuda"),
+           torch.empty(A.nnz, dtype=torch.int32, device="cuda"),
+           torch.empty(A.nnz, dtype=torch.float32, device="cuda"))
+    for _ in range(max(1, args.warmup)):
+        PA = binding.permute(dA, p, p, plan=plan, out=out)
+    perm_ms, PA = _wall(lambda: binding.permute(dA, p, p, plan=plan, out=out), args.steps)
+    assert plan.status() == binding.SPG_OK
+    perm_alg = 2 * csr_bytes(n, A.nnz, 4) + 4 * n
+    band = time_product(args, dA, dA)
+    perm = time_product(args, PA, PA)
+    gbs, frac = _roof(perm_alg, perm_ms)
+    return {"workload": "banded A 2^20 x 2^20, 16 per row on bands at offsets 0, +-2^17 "
+                        "(half-width 256), FP32; B = P A P^T with a random P",
+            "permute_ms": round(perm_ms, 4), "permute_alg_GBs": gbs, "permute_hbm_frac": frac,
+            "banded_AA_ms": round(band["ms_step"], 4), "permuted_AA_ms": round(perm["ms_step"], 4),
+            "banded_AA_gflops": round(2 * band["products"] / band["ms_step"] / 1e6, 2),
+            "permuted_AA_gflops": round(2 * perm["products"] / perm["ms_step"] / 1e6, 2),
+            "products": int(band["products"]), "nnz_AA": int(band["nnz"])}
 
 
 def traffic_from_profile(kernel_src_hash):
@@ -295,74 +442,87 @@ def main():
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--only-plain", action="store_true", help="skip the batched and backward workloads")
-    ap.add_argument("--mcl", action="store_true", help="also time 10 MCL iterations (n = 2^19)")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help=f"comma-separated further legs ({','.join(LEGS)}), or 'none'")
+    ap.add_argument("--only-plain", action="store_true", help="same as --legs none")
+    ap.add_argument("--skip-plain", action="store_true",
+                    help="run only the chosen legs (the headline fields are then absent)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by rows of A and C; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    legs = [] if (args.only_plain or args.legs == "none") else [x for x in args.legs.split(",") if x]
+    for leg in legs:
+        if leg not in LEGS:
+            ap.error(f"unknown leg {leg!r}")
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     n = 1 << args.log2n
     d = args.nnz_per_row
     log(f"[bench] generating A, B: {n} x {n}, {d} per row")
     A, B = make_inputs(n, d, SEED + 1)
-    log("[bench] plain product")
-    r = bench_plain(args, A, B)
-    products = r["products"]
-    gflops = 2.0 * products / (r["ms_step"] * 1e-3) / 1e9
-    num_bytes = csr_bytes(n, A.nnz, 4) + csr_bytes(n, B.nnz, 4) + 4 * (n + 1) + 8 * r["nnz"]
-    achieved = num_bytes / (r["num_ms"] * 1e-3) / 1e9
-    out = {
-        "metric": METRIC,
-        "value": round(gflops, 3),
-        "unit": "GFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(r["ms_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"C = A B, A and B independent uniform-random 2^{args.log2n} x 2^{args.log2n} "
-                        f"CSR, {d} nnz/row, int32 indices, FP32 values in (0,1], plain symbolic+numeric",
-            "rows": n, "nnz_per_row": d, "products": products, "nnz_C": r["nnz"], "seed": SEED + 1,
-        },
-        "roofline": {
-            "kernel": "numeric pass (row-binned LDS kernels: bucket placement, hash, sort fallback; all bins of one step)",
-            "bound": "hbm",
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profile(kernel_source_hash()),
-            "algorithmic_bytes": num_bytes,
-            "numeric_ms": round(r["num_ms"], 4),
-        },
+    out = {"metric": METRIC}
+    if not args.skip_plain:
+        log("[bench] plain product")
+        from paper_2603_21444_amd import binding
+        r = time_product(args, binding.to_device(A), binding.to_device(B))
+        torch.cuda.empty_cache()
+        products = r["products"]
+        gflops = 2.0 * products / (r["ms_step"] * 1e-3) / 1e9
+        num_bytes = csr_bytes(n, A.nnz, 4) + csr_bytes(n, B.nnz, 4) + 4 * (n + 1) + 8 * r["nnz"]
+        achieved = num_bytes / (r["num_ms"] * 1e-3) / 1e9
+        out.update({
+            "value": round(gflops, 3),
+            "unit": "GFLOP/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(r["ms_step"], 4),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32",
+            "data": "synthetic",
+            "config": {
+                "workload": f"C = A B, A and B independent uniform-random 2^{args.log2n} x 2^{args.log2n} "
+                            f"CSR, {d} nnz/row, int32 indices, FP32 values in (0,1], plain symbolic+numeric",
+                "rows": n, "nnz_per_row": d, "products": products, "nnz_C": r["nnz"], "seed": SEED + 1,
+            },
+            "roofline": {
+                "kernel": "numeric pass (row-binned LDS kernels: bucket placement, hash, sort fallback; all bins of one step)",
+                "bound": "hbm",
+                "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS,
+                "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profile(kernel_source_hash()),
+                "algorithmic_bytes": num_bytes,
+                "numeric_ms": round(r["num_ms"], 4),
+            },
+        })
+    runners = {
+        "batched": lambda: bench_batched(args),
+        "rmat": lambda: bench_batched_rmat(args),
+        "backward": lambda: bench_backward(args),
+        "mcl": lambda: bench_mcl(args, "workload"),
+        "mcl_paper": lambda: bench_mcl(args, "paper"),
+        "restriction": lambda: bench_restriction(args, A),
+        "permute": lambda: bench_permute(args),
     }
-    if not args.only_plain:
-        log("[bench] batched stage sequence")
-        out["batched_graph"] = bench_batched(args)
+    names = {"batched": "batched_graph", "rmat": "batched_graph_rmat", "mcl": "mcl",
+             "mcl_paper": "mcl_paper_order", "backward": "backward", "restriction": "restriction",
+             "permute": "permute"}
+    for leg in legs:
+        log(f"[bench] {leg}")
+        out[names[leg]] = runners[leg]()
         torch.cuda.empty_cache()
-        log("[bench] batched stage sequence, R-MAT")
-        out["batched_graph_rmat"] = bench_batched_rmat(args)
-        torch.cuda.empty_cache()
-        log("[bench] backward")
-        out["backward"] = bench_backward(args)
-        torch.cuda.empty_cache()
-    if args.mcl:
-        log("[bench] MCL")
-        out["mcl"] = bench_mcl(args)
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
-    if args.cpu_budget > 0:
+    if args.cpu_budget > 0 and not args.skip_plain:
         log("[bench] oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(A, B, args.cpu_budget)
     print(json.dumps(out), flush=True)

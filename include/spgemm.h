@@ -117,8 +117,9 @@ const char *spgemm_status_string(int status);
  * bins by products per row.  The numeric pass reuses the symbolic bins (a
  * row's products bound its nnz, so a table sized for them holds the row):
  * num_counts equals sym_counts.  Bin b >= 1 holds rows with key in
- * (8*2^(b-1), 8*2^b] (bin 1: 1..16), bin 0 empty rows, bin 12 the rows
- * beyond every LDS table of the pass in question.
+ * (e[b-1], e[b]] with e[b] = 8*2^b by default (bin 1: 1..16) or the tuned
+ * spg_tuning.bin_edge, bin 0 empty rows, bin 12 the rows beyond every LDS
+ * table of the pass in question.
  * SPG_ERR_ARG if the counts were not read back (capture-safe call). */
 int spgemm_plan_bins(spg_plan plan, int32_t *sym_counts, int32_t *num_counts);
 
@@ -267,6 +268,27 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
                          float *Y_vals, int64_t capacity, int64_t *Y_nnz_host,
                          void *workspace, size_t ws_bytes, void *stream);
 
+/* The same iteration in either step order.
+ *   SPG_MCL_INFLATE_FIRST  as spgemm_mcl_iteration above.
+ *   SPG_MCL_PAPER          the order §5.7 describes for the paper's own runs:
+ *                          E = X X; divide each row by its sum; drop
+ *                          e < prune; keep the topk largest (ties to the
+ *                          smaller column); an emptied row keeps its largest
+ *                          entry; e <- e^r for every kept entry, with no
+ *                          second normalisation (the next iteration's
+ *                          normalisation does it).  With prune > 0 at most
+ *                          1/prune entries survive per row, so topk =
+ *                          floor(1/prune) leaves the top-k step inactive and
+ *                          sizes the capacity (the paper's 0.002: 500).
+ * Arguments, capacity, workspace and errors as for spgemm_mcl_iteration. */
+#define SPG_MCL_INFLATE_FIRST 0
+#define SPG_MCL_PAPER 1
+int spgemm_mcl_iteration_order(spg_plan plan, const spg_csr *X, int32_t order, int32_t r,
+                               float prune, int32_t topk, int32_t *Y_row_ptr,
+                               int32_t *Y_col_idx, float *Y_vals, int64_t capacity,
+                               int64_t *Y_nnz_host, void *workspace, size_t ws_bytes,
+                               void *stream);
+
 /* ------------------------------------------------------------------------
  * Tuning (chosen by the autotuner outside any graph capture).
  * --------------------------------------------------------------------- */
@@ -278,6 +300,13 @@ typedef struct {
   int32_t sym_sub[SPG_NBINS];   /* the same for the symbolic count (power of 2, <= 64) */
   int32_t heavy_slots;          /* concurrent heavy rows (0 = as many as the workspace holds) */
   int32_t max_window;           /* longest hash probe kept in the fast numeric kernel (1..32) */
+  int32_t bin_edge[SPG_NBINS];  /* upper products-per-row key of LDS bin b of the product
+                                   passes, 1..8*2^b, or 0 for 8*2^b (the bin's table size / 2).
+                                   Rows with keys in (bin_edge[b], 8*2^b] go to bin b+1, whose
+                                   tables are twice as large: the edge sets both the bin
+                                   threshold and the table load factor of those rows.
+                                   Effective edges are made non-decreasing; the last LDS bin
+                                   always keeps its full edge.  MCL keeps the default edges. */
 } spg_tuning;
 
 int spgemm_default_tuning(spg_tuning *t);

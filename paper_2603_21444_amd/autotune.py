@@ -1,12 +1,17 @@
-"""Autotuner for the row kernels' launch parameters.
+"""Autotuner for the row kernels' launch parameters and the bin thresholds.
 
 For each bin that carries a noticeable share of the work it times the
 symbolic + numeric passes (HIP events, eager, outside any graph capture)
 over a few candidate (lanes per row, lanes per A entry) pairs, then over the
-symbolic pass's own lanes per A entry, and keeps the fastest; the other bins
-keep their current setting.  Results are cached in
-a JSON file keyed by dtype, shape, number of block products and the
-rounded per-bin row histogram, so a capture reuses them without timing.
+symbolic pass's own lanes per A entry, then over the bin's upper threshold
+(a fraction of the products its LDS tables are sized for: the rows above
+the threshold move to the next bin, whose tables are twice as large, so the
+threshold is also the table load factor of those rows), and keeps the
+fastest; the other bins keep their current setting.  This is the
+architecture-specific tuning of LDS (shared memory) use and team sizes the
+paper's local kernels rely on (§4.4).  Results are cached in a JSON file
+keyed by dtype, shape, number of block products and the rounded per-bin row
+histogram, so a capture reuses them without timing.
 """
 from __future__ import annotations
 
@@ -35,6 +40,15 @@ CANDIDATES = {
 }
 # candidate lanes per A entry of the symbolic count
 SYM_SUB_CANDIDATES = (4, 8, 16, 32)
+# candidate upper thresholds of a bin, as fractions of its table capacity
+EDGE_FRACTIONS = (1.0, 0.75, 0.5)
+# the last LDS bin of the product passes keeps its full edge
+LAST_TUNED_EDGE_BIN = 10
+
+
+def edge_for(b: int, frac: float) -> int:
+    """Threshold of bin b at the given fraction of its capacity (0 = full)."""
+    return 0 if frac >= 1.0 else max(1, int(BIN_EDGES[b] * frac))
 
 
 def default_cache_path() -> str:
@@ -100,6 +114,17 @@ def tune(As, Bs, reps: int = 3, cache_path: str | None = None, share: float = 0.
             if ms < best_ms:
                 best_s, best_ms = s, ms
         t.sym_sub[b] = best_s
+        if b <= LAST_TUNED_EDGE_BIN:
+            best_e = t.bin_edge[b]
+            for f in EDGE_FRACTIONS:
+                e = edge_for(b, f)
+                if e == best_e:
+                    continue
+                t.bin_edge[b] = e
+                ms = _time(As, Bs, t, reps)
+                if ms < best_ms:
+                    best_e, best_ms = e, ms
+            t.bin_edge[b] = best_e
     if use_cache:
         cache[key] = _to_json(t)
         os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -110,7 +135,8 @@ def tune(As, Bs, reps: int = 3, cache_path: str | None = None, share: float = 0.
 
 def _to_json(t: binding.SpgTuning) -> dict:
     return {"lanes": list(t.lanes), "sub": list(t.sub), "sym_sub": list(t.sym_sub),
-            "heavy_slots": t.heavy_slots, "max_window": t.max_window}
+            "bin_edge": list(t.bin_edge), "heavy_slots": t.heavy_slots,
+            "max_window": t.max_window}
 
 
 def _from_json(d: dict) -> binding.SpgTuning:
@@ -121,18 +147,21 @@ def _from_json(d: dict) -> binding.SpgTuning:
         t.sub[b] = v
     for b, v in enumerate(d.get("sym_sub", [])):
         t.sym_sub[b] = v
+    for b, v in enumerate(d.get("bin_edge", [])):
+        t.bin_edge[b] = v
     t.heavy_slots = d["heavy_slots"]
     t.max_window = d["max_window"]
     return t
 
 
 def describe(t: binding.SpgTuning, bins=range(1, 12)) -> dict:
-    """Compact record of a tuning for reports: per LDS bin, lanes per row,
-    lanes per A entry (numeric, symbolic)."""
+    """Compact record of a tuning for reports: per LDS bin that differs from
+    the default, lanes per row, lanes per A entry (numeric, symbolic) and the
+    bin's upper threshold (0 = its table capacity)."""
     d = binding.default_tuning()
     out = {}
     for b in bins:
-        cur = (t.lanes[b], t.sub[b], t.sym_sub[b])
-        if cur != (d.lanes[b], d.sub[b], d.sym_sub[b]):
+        cur = (t.lanes[b], t.sub[b], t.sym_sub[b], t.bin_edge[b])
+        if cur != (d.lanes[b], d.sub[b], d.sym_sub[b], d.bin_edge[b]):
             out[str(b)] = list(cur)
     return {"changed_bins": out, "heavy_slots": t.heavy_slots, "max_window": t.max_window}

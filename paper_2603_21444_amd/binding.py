@@ -26,6 +26,8 @@ SPG_ERR_CAPACITY, SPG_ERR_WORKSPACE, SPG_ERR_HIP, SPG_ERR_UNSUPPORTED, SPG_ERR_A
 SPG_ERR_SCRATCH = 9
 SPG_SCRATCH_BYTES = 128 << 20
 SPG_F32, SPG_F64 = 0, 1
+SPG_MCL_INFLATE_FIRST, SPG_MCL_PAPER = 0, 1
+MCL_ORDERS = {"workload": SPG_MCL_INFLATE_FIRST, "paper": SPG_MCL_PAPER}
 SPG_FLAG_VALIDATE = 1
 SPG_MAX_PARTS = 16
 SPG_NBINS = 16
@@ -35,7 +37,7 @@ EXPORTS = [
     "spgemm_plan_create", "spgemm_plan_destroy", "spgemm_workspace_size",
     "spgemm_plan_status", "spgemm_plan_clear_status", "spgemm_plan_info", "spgemm_status_string",
     "spgemm_symbolic", "spgemm_symbolic_noalloc", "spgemm_numeric", "spgemm_merge", "spgemm_backward",
-    "spgemm_mcl_workspace_size", "spgemm_mcl_iteration",
+    "spgemm_mcl_workspace_size", "spgemm_mcl_iteration", "spgemm_mcl_iteration_order",
     "spgemm_permute_workspace_size", "spgemm_permute",
     "spgemm_default_tuning", "spgemm_plan_set_tuning", "spgemm_plan_bins",
 ]
@@ -49,7 +51,8 @@ class SpgCsr(C.Structure):
 class SpgTuning(C.Structure):
     _fields_ = [("lanes", C.c_int32 * SPG_NBINS), ("sub", C.c_int32 * SPG_NBINS),
                 ("sym_sub", C.c_int32 * SPG_NBINS),
-                ("heavy_slots", C.c_int32), ("max_window", C.c_int32)]
+                ("heavy_slots", C.c_int32), ("max_window", C.c_int32),
+                ("bin_edge", C.c_int32 * SPG_NBINS)]
 
 
 class SpgError(RuntimeError):
@@ -90,6 +93,8 @@ def lib():
                                                C.POINTER(I64), P, C.c_size_t, P]),
             "spgemm_permute_workspace_size": (C.c_int, [I32, I32, C.POINTER(C.c_size_t)]),
             "spgemm_permute": (C.c_int, [P, PC, P, P, C.c_int, P, P, P, P, C.c_size_t, P]),
+            "spgemm_mcl_iteration_order": (C.c_int, [P, PC, I32, I32, C.c_float, I32, P, P, P,
+                                                     I64, C.POINTER(I64), P, C.c_size_t, P]),
             "spgemm_default_tuning": (C.c_int, [C.POINTER(SpgTuning)]),
             "spgemm_plan_set_tuning": (C.c_int, [P, C.POINTER(SpgTuning)]),
             "spgemm_plan_bins": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
@@ -362,12 +367,14 @@ def mcl_workspace_size(n: int, topk: int) -> int:
 
 def mcl_iteration(X: DeviceCSR, r: int = 2, prune: float = 1e-4, topk: int = 1000,
                   plan: Plan | None = None, out=None, stream=None,
-                  capture: bool = False, capacity: int | None = None) -> DeviceCSR:
+                  capture: bool = False, capacity: int | None = None,
+                  order: str = "workload") -> DeviceCSR:
     """One Markov-clustering iteration on X = M^T (FP32).  `out` may hold
     preallocated (row_ptr, col_idx, vals) of `capacity` entries (default
     n*min(topk, n), which always suffices).  With capture=True nothing is
     read back (graph-capturable); the result then spans the whole capacity
-    and its length is row_ptr[n]."""
+    and its length is row_ptr[n].  order: "workload" (inflate, normalise,
+    prune, top-k, renormalise) or "paper" (normalise, prune, top-k, power)."""
     torch = _torch()
     plan = plan or Plan()
     n = X.shape[0]
@@ -383,10 +390,11 @@ def mcl_iteration(X: DeviceCSR, r: int = 2, prune: float = 1e-4, topk: int = 100
     rp, col, vals = out
     nnz = C.c_int64(-1)
     x = X.spg()
-    _check(lib().spgemm_mcl_iteration(plan.h, C.byref(x), r, C.c_float(prune), topk, _ptr(rp),
-                                      _ptr(col), _ptr(vals), cap,
-                                      None if capture else C.byref(nnz), _ptr(plan.ws),
-                                      plan.ws.numel(), _stream(stream)), "spgemm_mcl_iteration")
+    _check(lib().spgemm_mcl_iteration_order(plan.h, C.byref(x), MCL_ORDERS[order], r,
+                                            C.c_float(prune), topk, _ptr(rp), _ptr(col),
+                                            _ptr(vals), cap, None if capture else C.byref(nnz),
+                                            _ptr(plan.ws), plan.ws.numel(), _stream(stream)),
+           "spgemm_mcl_iteration_order")
     if capture:
         return DeviceCSR((n, n), rp, col, vals)
     k = int(nnz.value)

@@ -150,6 +150,7 @@ spg_tuning default_tuning() {
   }
   t.heavy_slots = 0;
   t.max_window = kTail;
+  for (int b = 0; b < kNB; ++b) t.bin_edge[b] = 0;  // 0: the table capacity 8 * 2^b
   return t;
 }
 
@@ -162,7 +163,22 @@ int check_tuning(const spg_tuning &t) {
     if (!pow2(t.sym_sub[b]) || t.sym_sub[b] > 64) return SPG_ERR_ARG;
   }
   if (t.heavy_slots < 0 || t.max_window < 1 || t.max_window > kTail) return SPG_ERR_ARG;
+  for (int b = 1; b < kNB; ++b)
+    if (t.bin_edge[b] < 0 || t.bin_edge[b] > bin_edge(b)) return SPG_ERR_ARG;
   return SPG_OK;
+}
+
+// Upper keys of the product bins from the tuning: the tuned edge of each
+// LDS bin (at most its table capacity), non-decreasing, and the last LDS bin
+// always up to its capacity (rows above it are heavy rows either way).
+BinEdges tuned_edges(const spg_tuning &t, int maxbin) {
+  BinEdges E = default_edges();
+  for (int b = 1; b < maxbin && b < kNB; ++b) {
+    int32_t u = t.bin_edge[b] > 0 ? t.bin_edge[b] : (int32_t)bin_edge(b);
+    if (u < E.up[b - 1]) u = E.up[b - 1];
+    E.up[b] = u;
+  }
+  return E;
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SPG_OK : SPG_ERR_HIP; }
@@ -254,7 +270,8 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
     }
   }
   // a1 + a2: products per row and bins by products
-  e = launch_binning(dpr, m, D.sym_maxbin, L, ws, C_row_ptr, st);
+  e = launch_binning(dpr, m, D.sym_maxbin, tuned_edges(p->tun, D.sym_maxbin), L, ws, C_row_ptr,
+                     st);
   if (e != hipSuccess) return SPG_ERR_HIP;
   BinPlan sbp;
   if (eager) {
@@ -668,7 +685,17 @@ int spgemm_mcl_workspace_size(int32_t n, int32_t topk, size_t *bytes) {
 int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune, int32_t topk,
                          int32_t *Y_row_ptr, int32_t *Y_col_idx, float *Y_vals, int64_t capacity,
                          int64_t *Y_nnz_host, void *workspace, size_t ws_bytes, void *stream) {
+  return spgemm_mcl_iteration_order(plan, X, SPG_MCL_INFLATE_FIRST, r, prune, topk, Y_row_ptr,
+                                    Y_col_idx, Y_vals, capacity, Y_nnz_host, workspace, ws_bytes,
+                                    stream);
+}
+
+int spgemm_mcl_iteration_order(spg_plan plan, const spg_csr *X, int32_t order, int32_t r,
+                               float prune, int32_t topk, int32_t *Y_row_ptr, int32_t *Y_col_idx,
+                               float *Y_vals, int64_t capacity, int64_t *Y_nnz_host,
+                               void *workspace, size_t ws_bytes, void *stream) {
   if (!plan || !X || !Y_row_ptr) return SPG_ERR_ARG;
+  if (order != SPG_MCL_INFLATE_FIRST && order != SPG_MCL_PAPER) return SPG_ERR_ARG;
   if (X->nrows != X->ncols) return SPG_ERR_SHAPE;
   if (r < 1 || r > 8 || topk < 1 || !(prune >= 0.f) || !(prune < 1e30f)) return SPG_ERR_ARG;
   if (X->ncols > kMclMaxCols) return SPG_ERR_UNSUPPORTED;  // 24-bit columns in the LDS tables
@@ -717,7 +744,7 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
   // most rows of that bin still fit the largest table; those whose probes
   // overflow go to the panel kernel with the heavier bins
   const int mcl_bins = D.mcl_maxbin + 1 < kHeavyBin ? D.mcl_maxbin + 1 : D.mcl_maxbin;
-  e = launch_binning(dpr, n, mcl_bins, L, ws, Y_row_ptr, st);
+  e = launch_binning(dpr, n, mcl_bins, default_edges(), L, ws, Y_row_ptr, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
   BinPlan bp;
   if (eager) {
@@ -729,7 +756,10 @@ int spgemm_mcl_iteration(spg_plan plan, const spg_csr *X, int32_t r, float prune
   } else {
     bp = make_binplan(plan, mcl_bins, false, nullptr);
   }
-  e = launch_mcl(dpr, bp, L, ws, r, prune, topk, cap, pcol, pval, Y_row_ptr, st);
+  // the exponent before the normalisation, and after the prune (0: renormalise)
+  const int rpre = order == SPG_MCL_PAPER ? 1 : r;
+  const int rpost = order == SPG_MCL_PAPER ? r : 0;
+  e = launch_mcl(dpr, bp, L, ws, rpre, rpost, prune, topk, cap, pcol, pval, Y_row_ptr, st);
   if (e != hipSuccess) return SPG_ERR_HIP;
   e = launch_scan(Y_row_ptr, n, capacity, L, ws, st);  // capacity < 0: unchecked
   if (e != hipSuccess) return SPG_ERR_HIP;

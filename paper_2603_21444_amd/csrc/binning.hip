@@ -64,7 +64,7 @@ __device__ __forceinline__ int brow_len(const SPG_GLOBAL int32_t *brp, int r) {
 }
 
 __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict__ pr,
-                                                      int maxbin, uint8_t *binid,
+                                                      int maxbin, BinEdges edges, uint8_t *binid,
                                                       int32_t *blockhist, int32_t *cnt_zero,
                                                       WsHeader *hdr) {
   __shared__ int hist[kNB];
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   }
   if (i < m) {
     if (key == 0) cnt_zero[i] = 0;
-    int b = bin_of(key, maxbin);
+    int b = bin_of(key, maxbin, edges);
     binid[i] = (uint8_t)b;
     atomicAdd(&hist[b], 1);
   }
@@ -319,6 +319,12 @@ __global__ __launch_bounds__(256) void k_scan_apply(int32_t *rp, int m, const in
 
 // Host launchers.
 
+BinEdges default_edges() {
+  BinEdges E{};
+  for (int b = 0; b < kNB; ++b) E.up[b] = (int32_t)bin_edge(b);
+  return E;
+}
+
 hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool reset,
                         bool clear_status, hipStream_t st) {
   hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, pr, dst, hdr, reset ? 1 : 0,
@@ -341,14 +347,14 @@ hipError_t launch_validate(const int32_t *rp, const int32_t *col, int rows, int 
   return hipGetLastError();
 }
 
-hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const WsLayout &L, char *ws,
-                          int32_t *cnt_zero, hipStream_t st) {
+hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const BinEdges &edges,
+                          const WsLayout &L, char *ws, int32_t *cnt_zero, hipStream_t st) {
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   const int nblk = m == 0 ? 1 : (m + kBinBlock - 1) / kBinBlock;
   uint8_t *binid = reinterpret_cast<uint8_t *>(ws + L.binid);
   int32_t *bh = reinterpret_cast<int32_t *>(ws + L.blockhist);
   int32_t *rows = reinterpret_cast<int32_t *>(ws + L.rows);
-  hipLaunchKernelGGL(k_rowkey, dim3(nblk), dim3(kBinBlock), 0, st, dpr, maxbin,
+  hipLaunchKernelGGL(k_rowkey, dim3(nblk), dim3(kBinBlock), 0, st, dpr, maxbin, edges,
                      binid, bh, cnt_zero, hdr);
   hipLaunchKernelGGL(k_binscan, dim3(kNB), dim3(1024), 0, st, bh, nblk, hdr);
   hipLaunchKernelGGL(k_binscatter, dim3(nblk), dim3(kBinBlock), 0, st, binid, m, bh, rows, hdr);

@@ -33,6 +33,22 @@ __host__ __device__ inline int bin_of(int64_t key, int maxbin) {
   return b > maxbin ? kHeavyBin : b;
 }
 
+// Upper keys of the row bins as used by a binning pass: up[b] <= bin_edge(b)
+// (a row in bin b still fits the tables sized for bin_edge(b)), non-
+// decreasing, up[maxbin] = bin_edge(maxbin).  A lower up[b] sends the rows
+// with keys in (up[b], bin_edge(b)] to bin b + 1, whose tables are twice as
+// large: the bin threshold doubles as the table load factor of those rows.
+struct BinEdges {
+  int32_t up[kNB];
+};
+
+__host__ __device__ inline int bin_of(int64_t key, int maxbin, const BinEdges &E) {
+  if (key <= 0) return 0;
+  int b = 1;
+  while (b <= maxbin && key > E.up[b]) ++b;
+  return b > maxbin ? kHeavyBin : b;
+}
+
 // Hash table slots of an LDS bin: twice the bin's upper edge (load <= 1/2).
 __host__ __device__ inline int bin_slots(int b) { return (int)(2 * bin_edge(b)); }
 

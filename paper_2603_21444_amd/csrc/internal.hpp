@@ -61,7 +61,10 @@ hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool res
 hipError_t launch_clear_status(WsHeader *hdr, hipStream_t st);
 hipError_t launch_validate(const int32_t *rp, const int32_t *col, int rows, int ncols,
                            int64_t nnz, WsHeader *hdr, hipStream_t st);
-hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const WsLayout &L, char *ws,
+// Default edges: up[b] = bin_edge(b).
+BinEdges default_edges();
+hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const BinEdges &edges,
+                          const WsLayout &L, char *ws,
                           int32_t *cnt_zero, hipStream_t st);
 hipError_t launch_scan(int32_t *rp, int m, int64_t capacity, const WsLayout &L, char *ws,
                        hipStream_t st);
@@ -77,9 +80,11 @@ hipError_t launch_backward(const Problem *dpr, const BinPlan &bp, const WsLayout
                            int64_t nnzA, void *dB, int64_t nnzB, int dtype, hipStream_t st);
 hipError_t configure_backward_lds(size_t lds_max);
 
+// rpre: exponent before the normalisation; rpost: 0 = renormalise after the
+// prune and top-k, else the exponent applied to the kept entries instead.
 hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
-                      int r, float prune, int topk, int cap, int32_t *pcol, float *pval,
-                      int32_t *ycnt, hipStream_t st);
+                      int rpre, int rpost, float prune, int topk, int cap, int32_t *pcol,
+                      float *pval, int32_t *ycnt, hipStream_t st);
 hipError_t launch_mcl_compact(int n, int cap, const int32_t *yrp, const int32_t *pcol,
                               const float *pval, int32_t *ycol, float *yval, const WsHeader *hdr,
                               hipStream_t st);

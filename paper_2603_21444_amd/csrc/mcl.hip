@@ -1,7 +1,15 @@
-// One Markov-clustering iteration (a8; paper §5.7) on X = M^T in CSR, FP32:
-//   E = X X;  e <- e^r;  row /= row sum;  drop e < prune;  keep the topk
-//   largest (ties to the smaller column);  an emptied row keeps its largest
-//   entry;  row /= new row sum.
+// One Markov-clustering iteration (a8; paper §5.7) on X = M^T in CSR, FP32,
+// in one of two step orders:
+//   rpost == 0 (the synthetic workload's order):
+//     E = X X;  e <- e^r;  row /= row sum;  drop e < prune;  keep the topk
+//     largest (ties to the smaller column);  an emptied row keeps its
+//     largest entry;  row /= new row sum.
+//   rpost >= 1 (the order the paper describes for its runs):
+//     E = X X;  row /= row sum;  drop e < prune;  top-k and emptied rows as
+//     above;  e <- e^rpost;  no second normalisation.
+// Both are the same kernels with the exponent before the normalisation
+// (rpre = r, or 1) and the final step (renormalise, or the power) as
+// parameters.
 // The unpruned product is never stored.  Row c of Y is written at its final
 // column rank into a padded buffer (cap = min(topk, n) slots per row) with
 // its length in cnt[c]; a scan of cnt and a compaction copy produce CSR.
@@ -95,7 +103,8 @@ struct MclInsert {
 template <int G>
 __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
     const Problem *__restrict__ pr, const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
-    int bin, int lS, int TT, uint32_t mul, int maxwin, int r, float prune, int topk, int cap,
+    int bin, int lS, int TT, uint32_t mul, int maxwin, int r, int rpost, float prune, int topk,
+    int cap,
     int32_t *__restrict__ ycol, float *__restrict__ yval, int32_t *__restrict__ ycnt,
     int32_t *__restrict__ fb_rows) {
   using GM = MGeom<G>;
@@ -258,7 +267,7 @@ __global__ __launch_bounds__(MGeom<G>::WG) void k_mcl_rows(
         int rr = rk + (int)((uint32_t)w >> 24) - 128;
         rr = rr < 0 ? 0 : (rr >= cap ? cap - 1 : rr);
         cb[rr] = (int)((uint32_t)w & 0xffffffu);
-        vb[rr] = v / S2;
+        vb[rr] = rpost == 0 ? v / S2 : ipow(v, rpost);
         ++rk;
       }
     }
@@ -437,7 +446,7 @@ __device__ __forceinline__ int panel_accumulate(const SPG_GLOBAL int32_t *bcol,
 
 __global__ __launch_bounds__(kPT) void k_mcl_panel(
     const Problem *__restrict__ pr, const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
-    int blo, int r, float prune, int topk, int cap, const double *__restrict__ rabs,
+    int blo, int r, int rpost, float prune, int topk, int cap, const double *__restrict__ rabs,
     char *__restrict__ scratch, size_t slot_bytes, const int32_t *__restrict__ fb_rows,
     int32_t *__restrict__ ycol, float *__restrict__ yval, int32_t *__restrict__ ycnt) {
   extern __shared__ __align__(16) unsigned long long pacc[];
@@ -641,7 +650,7 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
         if (tid == 0) {
           const float q = __uint_as_float((uint32_t)(rowbest >> 32)) / S;
           cb[0] = (int)~(uint32_t)(rowbest & 0xffffffffu);
-          vb[0] = q / q;
+          vb[0] = rpost == 0 ? q / q : ipow(q, rpost);
         }
         outn = 1;
       }
@@ -653,7 +662,7 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
         const int o = outn + R.excl;
         if (sel && o < cap) {
           cb[o] = lcol[idx];
-          vb[o] = lval[idx] / S2;
+          vb[o] = rpost == 0 ? lval[idx] / S2 : ipow(lval[idx], rpost);
         }
         outn += R.total;
         __syncthreads();
@@ -709,11 +718,12 @@ __global__ __launch_bounds__(256) void k_mcl_compact(int n, int cap, const int32
 
 template <int G>
 static void mcl_launch(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin, int lS,
-                       int TT, uint32_t mul, int maxwin, int r, float prune, int topk, int cap,
+                       int TT, uint32_t mul, int maxwin, int r, int rpost, float prune, int topk,
+                       int cap,
                        int32_t *ycol, float *yval, int32_t *ycnt, int32_t *fb, int grid,
                        size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(k_mcl_rows<G>, dim3(grid), dim3(MGeom<G>::WG), lds, st, dpr, rows, hdr, bin,
-                     lS, TT, mul, maxwin, r, prune, topk, cap, ycol, yval, ycnt, fb);
+                     lS, TT, mul, maxwin, r, rpost, prune, topk, cap, ycol, yval, ycnt, fb);
 }
 
 size_t mcl_lds_bytes(int b, int G) {
@@ -723,7 +733,7 @@ size_t mcl_lds_bytes(int b, int G) {
 }
 
 hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
-                      int r, float prune, int topk, int cap, int32_t *pcol, float *pval,
+                      int r, int rpost, float prune, int topk, int cap, int32_t *pcol, float *pval,
                       int32_t *ycnt, hipStream_t st) {
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   const int32_t *rows = reinterpret_cast<const int32_t *>(ws + L.rows);
@@ -752,7 +762,7 @@ hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, 
     while ((1 << lS) < S) ++lS;
     switch (G) {
 #define SPG_MCL_CASE(g) \
-  case g: mcl_launch<g>(dpr, rows, hdr, b, lS, TT, mul, maxwin, r, prune, topk, cap, pcol, pval, ycnt, fb, grid, lds, st); break;
+  case g: mcl_launch<g>(dpr, rows, hdr, b, lS, TT, mul, maxwin, r, rpost, prune, topk, cap, pcol, pval, ycnt, fb, grid, lds, st); break;
       SPG_MCL_CASE(8)
       SPG_MCL_CASE(16)
       SPG_MCL_CASE(32)
@@ -760,7 +770,7 @@ hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, 
       SPG_MCL_CASE(128)
       SPG_MCL_CASE(256)
       SPG_MCL_CASE(512)
-      default: mcl_launch<1024>(dpr, rows, hdr, b, lS, TT, mul, maxwin, r, prune, topk, cap, pcol, pval, ycnt, fb, grid, lds, st);
+      default: mcl_launch<1024>(dpr, rows, hdr, b, lS, TT, mul, maxwin, r, rpost, prune, topk, cap, pcol, pval, ycnt, fb, grid, lds, st);
 #undef SPG_MCL_CASE
     }
   }
@@ -772,7 +782,7 @@ hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, 
     hipLaunchKernelGGL(k_row_abs, dim3(D.cus * 8), dim3(256), 0, st, dpr, hdr, rabs);
     const size_t lds = (size_t)kPanel * 8 + (size_t)kPanel / 8;
     hipLaunchKernelGGL(k_mcl_panel, dim3(grid), dim3(kPT), lds, st, dpr, rows, hdr, bp.maxbin + 1,
-                       r, prune, topk, cap, rabs, ws + L.mcl_slots, mcl_slot_bytes(bp.n), fb,
+                       r, rpost, prune, topk, cap, rabs, ws + L.mcl_slots, mcl_slot_bytes(bp.n), fb,
                        pcol, pval, ycnt);
   }
   return hipGetLastError();

@@ -74,10 +74,11 @@ class MCLGraph:
 
     def __init__(self, X: binding.DeviceCSR, iters: int = 10, r: int = 2,
                  prune: float = 1e-4, topk: int = 1000, tuning=None,
-                 capacity: int | None = None):
+                 capacity: int | None = None, order: str = "workload"):
         n = X.shape[0]
         dev = X.row_ptr.device
         self.n, self.iters, self.r, self.prune, self.topk = n, iters, r, prune, topk
+        self.order = order
         self.plan = binding.Plan(tuning=tuning)
         cap = n * min(topk, n) if capacity is None else int(capacity)
         self.capacity = cap
@@ -89,7 +90,7 @@ class MCLGraph:
         self.X0 = X
         # warm-up outside the capture: workspace, kernels
         binding.mcl_iteration(X, r, prune, topk, plan=self.plan, out=self.bufs[1],
-                              capacity=cap, capture=True)
+                              capacity=cap, capture=True, order=order)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         self.stream = torch.cuda.Stream()
@@ -106,7 +107,8 @@ class MCLGraph:
         for t in range(self.iters):
             dst = self.bufs[t % 2]
             binding.mcl_iteration(src, self.r, self.prune, self.topk, plan=self.plan, out=dst,
-                                  stream=stream, capture=True, capacity=self.capacity)
+                                  stream=stream, capture=True, capacity=self.capacity,
+                                  order=self.order)
             src = self._view(t % 2)
 
     def buffer(self, t: int) -> binding.DeviceCSR:

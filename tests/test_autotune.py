@@ -19,6 +19,22 @@ def test_every_candidate_is_accepted_by_the_library():
                 p.set_tuning(t)  # raises SpgError when rejected
 
 
+def test_every_edge_candidate_is_accepted_and_capacity_enforced():
+    p = binding.Plan()
+    for b in range(1, autotune.LAST_TUNED_EDGE_BIN + 1):
+        for f in autotune.EDGE_FRACTIONS:
+            t = binding.default_tuning()
+            t.bin_edge[b] = autotune.edge_for(b, f)
+            p.set_tuning(t)
+        t = binding.default_tuning()
+        t.bin_edge[b] = autotune.BIN_EDGES[b] + 1  # beyond the bin's tables
+        with pytest.raises(binding.SpgError):
+            p.set_tuning(t)
+        t.bin_edge[b] = -1
+        with pytest.raises(binding.SpgError):
+            p.set_tuning(t)
+
+
 def test_library_rejects_bad_symbolic_sub():
     p = binding.Plan()
     for bad in (0, 3, 128):
@@ -40,8 +56,10 @@ def test_json_round_trip():
     t = binding.default_tuning()
     t.lanes[5], t.sub[5], t.sym_sub[5] = 32, 8, 16
     t.heavy_slots = 7
+    t.bin_edge[6] = autotune.edge_for(6, 0.75)
     d = json.loads(json.dumps(autotune._to_json(t)))
     u = autotune._from_json(d)
+    assert list(u.bin_edge) == list(t.bin_edge)
     assert list(u.lanes) == list(t.lanes)
     assert list(u.sub) == list(t.sub)
     assert list(u.sym_sub) == list(t.sym_sub)
@@ -111,6 +129,15 @@ def test_every_candidate_gives_the_oracle_product(dtype):
         for b in range(1, 12):
             t.sub[b], t.sym_sub[b] = sub, ssub
         settings.append((f"sub {sub} sym_sub {ssub}", t))
+    for f in autotune.EDGE_FRACTIONS[1:] + (0.3,):
+        t = binding.default_tuning()
+        for b in range(1, 12):
+            t.bin_edge[b] = autotune.edge_for(b, f)
+        settings.append((f"bin edges at {f} of capacity", t))
+    t = binding.default_tuning()
+    for b in range(1, 12):  # decreasing raw edges: made non-decreasing by the library
+        t.bin_edge[b] = min(autotune.BIN_EDGES[b], 300 - 20 * b)
+    settings.append(("non-monotone edges", t))
     for what, t in settings:
         plan = binding.Plan(tuning=t)
         rp, nnz = plan.symbolic([dA], [dB])

@@ -27,6 +27,7 @@ def _check_step(X, got, r, prune, topk, rows=None):
     return check_mcl_step(X, got, r, prune, topk, rows)
 
 
+
 def test_hand_worked_golden(B):
     g = load_golden("mcl_hand.json")
     X = csr_from_json(g["X"], np.float32)
@@ -160,3 +161,85 @@ def test_rows_past_the_largest_table(B, window):
         t.max_window = window
     got = B.mcl_iteration(B.to_device(X), 2, 1e-4, 1000, plan=B.Plan(tuning=t)).to_host()
     _check_step(X, got, 2, 1e-4, 1000, np.array([3, 1999, 3999] + list(range(0, n, 37))))
+
+
+# ------------------------------------------- the paper's own step order (§5.7)
+def test_paper_order_hand_worked_golden(B):
+    g = load_golden("mcl_paper_hand.json")
+    X = csr_from_json(g["X"], np.float32)
+    for case in g["cases"]:
+        Y = B.mcl_iteration(B.to_device(X), case["r"], case["prune"], case["topk"],
+                            order="paper").to_host()
+        for i, (ecols, evals) in enumerate(case["rows"]):
+            s, e = Y.indptr[i], Y.indptr[i + 1]
+            assert Y.indices[s:e].tolist() == ecols, (case, i)
+            assert np.allclose(Y.data[s:e], [p / q for p, q in evals], rtol=2e-6, atol=0), (case, i)
+
+
+@pytest.mark.parametrize("b", [4, 64, 256])
+def test_paper_order_block_fixed_point(B, b):
+    """Blocks of 1/b become blocks of 1/b^2 after one iteration and stay
+    there (E = 1/b^3, normalised 1/b, squared 1/b^2): exact in FP32 for b a
+    power of 2, through the LDS tables (b <= 64) and the panel kernel
+    (b = 256: 65536 products per row)."""
+    nb = 5
+    n = b * nb
+    perm = synth.rng_for(b, 3).permutation(n)
+    rows, cols = [], []
+    for blk in perm.reshape(nb, b):
+        for i in blk:
+            for j in blk:
+                rows.append(i); cols.append(j)
+    rows, cols = np.array(rows), np.array(cols)
+    order = np.lexsort((cols, rows))
+    ip = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=ip[1:])
+    X = synth.HostCSR((n, n), ip, cols[order].astype(np.int32), np.full(n * b, 1.0 / b, np.float32))
+    Y = B.to_device(X)
+    for _ in range(10):
+        Y = B.mcl_iteration(Y, 2, 0.002, 500, order="paper")
+        H = Y.to_host()
+        assert np.array_equal(H.indptr, X.indptr)
+        assert np.array_equal(H.indices, X.indices)
+        assert np.all(H.data == np.float32(1.0 / (b * b)))
+
+
+@pytest.mark.parametrize("n,d,prune,topk", [(3000, 12, 0.002, 500), (20000, 24, 0.002, 500),
+                                            (20000, 24, 1e-3, 50)])
+def test_paper_order_stepwise_random(B, n, d, prune, topk):
+    X = synth.mcl_matrix(n, d, 37, np.float32)
+    Y = B.to_device(X)
+    Xh = X
+    for it in range(3):
+        Yn = B.mcl_iteration(Y, 2, prune, topk, order="paper")
+        got = Yn.to_host()
+        rows = None if n <= 3000 else np.sort(synth.rng_for(it, 6).choice(n, 1500, replace=False))
+        check_mcl_step(Xh, got, 2, prune, topk, rows, order="paper")
+        lens = np.diff(got.indptr)
+        assert lens.max() <= topk and lens.min() >= 1
+        assert got.data.min() >= np.float32(prune) ** 2 * (1 - 1e-5) or lens.min() == 1
+        Y, Xh = Yn, got
+
+
+@pytest.mark.parametrize("r,topk,prune", [(2, 500, 0.002), (2, 30, 1e-4), (3, 1000, 1e-5)])
+def test_paper_order_heavy_rows(B, r, topk, prune):
+    """Rows beyond every LDS table in the paper's order (the panel kernel
+    keeps every column as a candidate, since the exponent before the
+    normalisation is 1)."""
+    n = 30000
+    X = _heavy_input(n)
+    got = B.mcl_iteration(B.to_device(X), r, prune, topk, order="paper").to_host()
+    rows = np.array([7, 1234, 29999] + list(range(0, n, 97)))
+    check_mcl_step(X, got, r, prune, topk, rows, order="paper")
+
+
+def test_paper_order_graph_last_step(B):
+    from paper_2603_21444_amd.graph import MCLGraph
+    n = 5000
+    X = synth.mcl_matrix(n, 16, 19, np.float32)
+    g = MCLGraph(B.to_device(X), iters=10, r=2, prune=0.002, topk=500, order="paper")
+    for _ in range(2):
+        g.replay()
+        got = g.result().to_host()
+        prev = g.buffer(8).to_host()
+        check_mcl_step(prev, got, 2, 0.002, 500, order="paper")
