@@ -295,7 +295,9 @@ int spgemm_mcl_iteration_order(spg_plan plan, const spg_csr *X, int32_t order, i
 #define SPG_NBINS 16
 
 typedef struct {
-  int32_t lanes[SPG_NBINS];     /* threads cooperating on one row, per bin (power of 2, 8..1024) */
+  int32_t lanes[SPG_NBINS];     /* threads cooperating on one row, per bin (power of 2, 8..1024;
+                                   bin 1 also 1: one thread per row, products sorted in
+                                   registers) */
   int32_t sub[SPG_NBINS];       /* threads sharing one A entry's B row, per bin (power of 2, <= 64) */
   int32_t sym_sub[SPG_NBINS];   /* the same for the symbolic count (power of 2, <= 64) */
   int32_t heavy_slots;          /* concurrent heavy rows (0 = as many as the workspace holds) */

@@ -26,7 +26,7 @@ from . import binding
 BIN_EDGES = [0] + [8 << b for b in range(1, 12)]
 # candidate (lanes, sub) per bin size class
 CANDIDATES = {
-    1: [(8, 4), (8, 8), (16, 8)],
+    1: [(8, 4), (8, 8), (16, 8), (1, 1)],
     2: [(8, 8), (16, 8), (16, 16)],
     3: [(16, 8), (16, 16), (32, 16)],
     4: [(32, 8), (32, 16), (64, 16)],

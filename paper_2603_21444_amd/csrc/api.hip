@@ -38,6 +38,10 @@ struct spg_plan_s {
   // capture-safe call clears it only on first use of a workspace, so an
   // error raised by one call of a captured sequence reaches the end of it
   const void *status_ws = nullptr;
+  // lanes per A entry never exceed the mean B row length rounded up to a
+  // power of two: with short B rows (an aggregation operator has one entry
+  // per row) wider groups would leave lanes idle
+  int sub_cap = 64;
 };
 
 namespace spg {
@@ -158,7 +162,9 @@ bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 int check_tuning(const spg_tuning &t) {
   for (int b = 1; b < kNB; ++b) {
-    if (!pow2(t.lanes[b]) || t.lanes[b] < 8 || t.lanes[b] > 1024) return SPG_ERR_ARG;
+    const bool one_per_row = b == 1 && t.lanes[b] == 1;  // bin 1 only
+    if (!one_per_row && (!pow2(t.lanes[b]) || t.lanes[b] < 8 || t.lanes[b] > 1024))
+      return SPG_ERR_ARG;
     if (!pow2(t.sub[b]) || t.sub[b] > 64) return SPG_ERR_ARG;
     if (!pow2(t.sym_sub[b]) || t.sym_sub[b] > 64) return SPG_ERR_ARG;
   }
@@ -204,6 +210,20 @@ int status_from_bits(int bits) {
   return SPG_OK;
 }
 
+// Mean B row length (the products of one A entry), rounded up to a power of
+// two, at most 64.
+int sub_cap_for(int K, const spg_csr *B) {
+  int64_t nz = 0, rows = 0;
+  for (int k = 0; k < K; ++k) {
+    nz += B[k].nnz;
+    rows += B[k].nrows;
+  }
+  const int64_t mean = rows > 0 ? (nz + rows - 1) / rows : 1;
+  int c = 1;
+  while (c < mean && c < 64) c <<= 1;
+  return c;
+}
+
 BinPlan make_binplan(spg_plan p, int maxbin, bool counts_known, const int *counts,
                      bool symbolic = false) {
   BinPlan bp;
@@ -213,6 +233,7 @@ BinPlan make_binplan(spg_plan p, int maxbin, bool counts_known, const int *count
   for (int b = 0; b < kNB; ++b) {
     bp.lanes[b] = p->tun.lanes[b];
     bp.sub[b] = symbolic ? p->tun.sym_sub[b] : p->tun.sub[b];
+    if (bp.sub[b] > p->sub_cap) bp.sub[b] = p->sub_cap;
   }
   bp.maxbin = maxbin;
   bp.heavy_slots = p->L.heavy_slots;
@@ -239,6 +260,7 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
   p->ws = static_cast<char *>(workspace);
   p->ws_bytes = ws_bytes;
   p->status_ws = workspace;
+  p->sub_cap = sub_cap_for(pr.K, B);
   p->L = L;
   p->crp = C_row_ptr;
   p->stream = st;
@@ -718,6 +740,7 @@ int spgemm_mcl_iteration_order(spg_plan plan, const spg_csr *X, int32_t order, i
   plan->ws = static_cast<char *>(workspace);
   plan->ws_bytes = ws_bytes;
   plan->status_ws = workspace;
+  plan->sub_cap = sub_cap_for(1, X);
   plan->L = L;
   plan->stream = st;
   plan->m = plan->n = n;

@@ -159,7 +159,9 @@ __global__ __launch_bounds__(1024) void k_bwd_heavy(const Problem *__restrict__ 
   const int count = hdr->bin_start[kHeavyBin + 1] - start;
   const int tid = threadIdx.x;
   const Part &P = pr->part[0];
-  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+  __shared__ int item;
+  for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
+       ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
     const int i = rows[start + ri];
     const int rs = crp[i], re = crp[i + 1];
     for (int t = rs + tid; t < re; t += 1024) dense[ccol[t]] = w[t];
@@ -207,7 +209,7 @@ static hipError_t backward_impl(const Problem *dpr, const BinPlan &bp, const WsL
     hipLaunchKernelGGL(k_fill_zero<VT>, dim3(D.cus * 4), dim3(256), 0, st, dB, nnzB);
   for (int b = 1; b <= bp.maxbin; ++b) {
     if (bp.known && bp.count[b] == 0) continue;
-    int G = bp.lanes[b];
+    int G = bp.lanes[b] < 8 ? 8 : bp.lanes[b];  // no one-thread-per-row backward kernel
     while (G < 1024 && bwd_lds_bytes(b, G, sizeof(VT)) > D.lds_per_block) G *= 2;
     const int WG = G <= kWave ? 256 : G;
     const int R = WG / G;

@@ -31,8 +31,9 @@ __global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset, int 
   }
   if (threadIdx.x == 0) {
     hdr->fallback_count = 0;
-    hdr->heavy_cursor = 0;
+    hdr->long_count = 0;
   }
+  if (threadIdx.x < kNB + 2) hdr->queue[threadIdx.x] = 0;
 }
 
 // Optional validation of one CSR operand: row_ptr[0] == 0, non-decreasing,
@@ -54,8 +55,18 @@ __global__ void k_validate(const int32_t *rp, const int32_t *col, int rows, int 
 // reads its row's A columns four at a time (16-byte loads) and the bounds of
 // each selected B row with one 8-byte load: the rows of a wave's lanes lie
 // far apart, so every load instruction touches up to 64 cache lines and the
-// number of instructions is what costs.
+// number of instructions is what costs.  Rows of more than kKeyWave A
+// entries (over all block products) are summed by the whole wave; rows of
+// more than kKeyLong entries (power-law hubs, which often sit next to each
+// other) are left to k_rowkey_long, one block per row, so that no wave sums
+// several of them one after another.  A row of a few hundred entries spread
+// over the K block products stays with its thread: eight gathers in flight
+// per thread keep it short, while the wave would take its rows one by one.
 constexpr int kBinBlock = 256;
+constexpr int kKeyWave = 256;
+constexpr int kKeyLong = 2048;
+constexpr int kKeyLongBlock = 256;  // threads of k_rowkey_long
+constexpr uint8_t kBinDeferred = 0xff;
 
 __device__ __forceinline__ int brow_len(const SPG_GLOBAL int32_t *brp, int r) {
   int2 b;
@@ -66,7 +77,7 @@ __device__ __forceinline__ int brow_len(const SPG_GLOBAL int32_t *brp, int r) {
 __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict__ pr,
                                                       int maxbin, BinEdges edges, uint8_t *binid,
                                                       int32_t *blockhist, int32_t *cnt_zero,
-                                                      WsHeader *hdr) {
+                                                      int32_t *longrows, WsHeader *hdr) {
   __shared__ int hist[kNB];
   __shared__ long long psum[kBinBlock / kWave];
   if (hdr->status) return;  // invalid operands or overflow: touch nothing
@@ -75,7 +86,7 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   const int m = pr->m;
   const int i = blockIdx.x * kBinBlock + threadIdx.x;
   int64_t key = 0;
-  bool longrow = false;
+  bool longrow = false, deferred = false;
   if (i < m) {
     const int K = pr->K;
     int len = 0;
@@ -84,8 +95,12 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
       a_row(pr->part[k], i, as, ae);
       len += ae - as;
     }
-    longrow = len > kWave;  // counted by the whole wave below
-    for (int k = 0; k < K && !longrow; ++k) {
+    longrow = len > kKeyWave;  // counted by the whole wave below
+    if (len > kKeyLong) {  // counted by k_rowkey_long
+      longrow = false;
+      deferred = true;
+    }
+    for (int k = 0; k < K && !longrow && !deferred; ++k) {
       const Part &P = pr->part[k];
       int as, ae;
       a_row(P, i, as, ae);
@@ -132,7 +147,10 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
     for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
     if (lane_id() == lead) key = part;
   }
-  if (i < m) {
+  if (i < m && deferred) {
+    binid[i] = kBinDeferred;
+    longrows[atomicAdd(&hdr->long_count, 1)] = i;
+  } else if (i < m) {
     if (key == 0) cnt_zero[i] = 0;
     int b = bin_of(key, maxbin, edges);
     binid[i] = (uint8_t)b;
@@ -149,6 +167,55 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
     long long s = 0;
     for (int w = 0; w < kBinBlock / kWave; ++w) s += psum[w];
     atomicAdd((unsigned long long *)&hdr->products_total, (unsigned long long)s);
+  }
+}
+
+// Row keys of the rows k_rowkey deferred (more than kKeyLong A entries): one
+// block per row sums its B row lengths, then the row gets its bin, its place
+// in its block's histogram and its share of the product total.
+__global__ __launch_bounds__(kKeyLongBlock) void k_rowkey_long(const Problem *__restrict__ pr, int maxbin,
+                                                      BinEdges edges, uint8_t *binid,
+                                                      int32_t *blockhist, int nblk,
+                                                      int32_t *cnt_zero,
+                                                      const int32_t *__restrict__ longrows,
+                                                      WsHeader *hdr) {
+  __shared__ long long wsum[kKeyLongBlock / kWave];
+  if (hdr->status) return;
+  const int count = hdr->long_count;
+  const int tid = threadIdx.x;
+  for (int li = blockIdx.x; li < count; li += gridDim.x) {
+    const int i = longrows[li];
+    long long part = 0;
+    for (int k = 0; k < pr->K; ++k) {
+      const Part &P = pr->part[k];
+      int as, ae;
+      a_row(P, i, as, ae);
+      const SPG_GLOBAL int32_t *brp = gp(P.brp);
+      constexpr int NT = kKeyLongBlock;
+      int p = as + tid;
+      for (; p + 3 * NT < ae; p += 4 * NT) {  // four gathers in flight per thread
+        int r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, i, p + u * NT);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) part += brow_len(brp, r[u]);
+      }
+      for (; p < ae; p += NT) part += brow_len(brp, a_entry_row(P, i, p));
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (lane_id() == 0) wsum[tid / kWave] = part;
+    __syncthreads();
+    if (tid == 0) {
+      long long key = 0;
+      for (int w = 0; w < kKeyLongBlock / kWave; ++w) key += wsum[w];
+      if (key == 0) cnt_zero[i] = 0;
+      const int b = bin_of(key, maxbin, edges);
+      binid[i] = (uint8_t)b;
+      atomicAdd(&blockhist[(int64_t)b * nblk + i / kBinBlock], 1);
+      atomicAdd((unsigned long long *)&hdr->products_total, (unsigned long long)key);
+    }
+    __syncthreads();
   }
 }
 
@@ -354,8 +421,12 @@ hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const BinEdges 
   uint8_t *binid = reinterpret_cast<uint8_t *>(ws + L.binid);
   int32_t *bh = reinterpret_cast<int32_t *>(ws + L.blockhist);
   int32_t *rows = reinterpret_cast<int32_t *>(ws + L.rows);
+  int32_t *longrows = reinterpret_cast<int32_t *>(ws + L.fbrows);  // free until the row kernels
   hipLaunchKernelGGL(k_rowkey, dim3(nblk), dim3(kBinBlock), 0, st, dpr, maxbin, edges,
-                     binid, bh, cnt_zero, hdr);
+                     binid, bh, cnt_zero, longrows, hdr);
+  hipLaunchKernelGGL(k_rowkey_long, dim3(dev_info().cus * 4), dim3(kKeyLongBlock), 0, st, dpr,
+                     maxbin, edges,
+                     binid, bh, nblk, cnt_zero, longrows, hdr);
   hipLaunchKernelGGL(k_binscan, dim3(kNB), dim3(1024), 0, st, bh, nblk, hdr);
   hipLaunchKernelGGL(k_binscatter, dim3(nblk), dim3(kBinBlock), 0, st, binid, m, bh, rows, hdr);
   return hipGetLastError();

@@ -77,8 +77,26 @@ struct WsHeader {
   int32_t bin_count[kNB];
   int32_t bin_start[kNB + 1];
   int32_t fallback_count;
-  int32_t heavy_cursor;
+  int32_t long_count;  // rows the row-key kernel leaves to k_rowkey_long
+  int32_t queue[kNB + 2];  // work-queue cursors: per bin, fallback rows, heavy rows
 };
+static_assert(sizeof(WsHeader) <= 256, "the operand descriptors follow at byte 256");
+
+constexpr int kQueueFallback = kNB;
+constexpr int kQueueHeavy = kNB + 1;
+
+// Device work queue of a persistent launch: its blocks take the rows (items)
+// of their list one at a time from a cursor in the workspace header, so a
+// block that drew short rows takes more of them (the rows of one list can
+// differ in work by orders of magnitude: power-law hubs sit next to short
+// rows).  Thread 0 takes the item and the block reads it from LDS; the first
+// barrier keeps thread 0 from overwriting the previous item too early.
+__device__ __forceinline__ int block_next(int *cursor, int *item) {
+  __syncthreads();
+  if (threadIdx.x == 0) *item = atomicAdd(cursor, 1);
+  __syncthreads();
+  return *item;
+}
 
 // Operand arrays are read through global-address-space pointers: the
 // pointers come from memory (the device copy of the Problem), and without

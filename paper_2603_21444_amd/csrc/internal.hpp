@@ -109,6 +109,14 @@ size_t perm_workspace_bytes(int64_t m, int64_t n, size_t *rinv_off, size_t *cinv
 hipError_t launch_permute(const spg_csr &A, const int32_t *prow, const int32_t *pcol, int dtype,
                           int32_t *brp, int32_t *bcol, void *bval, char *ws, hipStream_t st);
 
+// One thread per row for bin 1 (at most 16 products per row): tuning lanes
+// value 1 selects these kernels.
+void launch_sym_tiny(const Problem *dpr, const int32_t *rows, const WsHeader *hdr, int bin,
+                     int count, bool known, int32_t *cnt, hipStream_t st);
+void launch_num_tiny(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin, int count,
+                     bool known, const int32_t *crp, int32_t *ccol, void *cval, bool f64,
+                     hipStream_t st);
+
 // LDS bytes of one block of the symbolic / numeric kernel of bin b with G
 // lanes per row.
 size_t sym_lds_bytes(int b, int G);

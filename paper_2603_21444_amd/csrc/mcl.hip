@@ -478,7 +478,9 @@ __global__ __launch_bounds__(kPT) void k_mcl_panel(
   for (int s = tid; s < kPanel / 32; s += kPT) pbm[s] = 0u;
   __syncthreads();
   const bool even = (r & 1) == 0;
-  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+  __shared__ int item;
+  for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
+       ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
     const int i = ri < nheavy ? rows[start + ri] : fb_rows[ri - nheavy];
     int as, ae;
     a_row(P, i, as, ae);
@@ -742,7 +744,7 @@ hipError_t launch_mcl(const Problem *dpr, const BinPlan &bp, const WsLayout &L, 
   const int maxwin = bp.maxwin < kTail ? bp.maxwin : kTail;
   for (int b = 1; b <= bp.maxbin; ++b) {
     if (bp.known && bp.count[b] == 0) continue;
-    int G = bp.lanes[b];
+    int G = bp.lanes[b] < 8 ? 8 : bp.lanes[b];  // no one-thread-per-row MCL kernel
     while (G < 1024 && mcl_lds_bytes(b, G) > D.lds_per_block) G *= 2;
     // a bin past the largest table that fits takes that table (rows whose
     // distinct columns overflow it are handed to the panel kernel)

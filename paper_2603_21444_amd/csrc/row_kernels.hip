@@ -367,14 +367,27 @@ struct BucketInsertB {
   uint32_t mul;
   int cap;
   bool over;
+  // LDS flag, raised once a bucket holds more than kBigBucket products: the
+  // row's columns cluster and it will be sorted as a whole, so the waves
+  // that see the flag stop taking bucket tickets (on which the lanes of a
+  // clustered row would contend for a few LDS words).  A stale read only
+  // means a few more tickets.
+  int *bigflag;
   template <int N>
   __device__ __forceinline__ void batch(const int (&col)[N], const VT (&v)[N]) {
     uint32_t old[N], sh[N];
+    const bool skip = *bigflag != 0;
 #pragma unroll
     for (int u = 0; u < N; ++u) {
       const uint32_t b = mono_slot((uint32_t)col[u], mul);
       sh[u] = (b & 1u) << 4;
-      old[u] = col[u] >= 0 ? atomicAdd(&cnt[b >> 1], 1u << sh[u]) : 0u;
+      old[u] = (col[u] >= 0 && !skip) ? atomicAdd(&cnt[b >> 1], 1u << sh[u]) : 0u;
+    }
+    if (!skip) {
+      bool hi = false;
+#pragma unroll
+      for (int u = 0; u < N; ++u) hi = hi || ((old[u] >> sh[u]) & 0xffffu) > (uint32_t)kBigBucket;
+      if (hi) *bigflag = 1;
     }
     uint64_t m[N];
     int tot = 0;
@@ -417,7 +430,7 @@ __global__ __launch_bounds__(G) void k_num_bucket_blk(
     int32_t *__restrict__ ccol, VT *__restrict__ cval, int32_t *__restrict__ fb_rows) {
   static_assert(G >= 128 && G <= 1024, "block groups only");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int wcount, overflow;
+  __shared__ int wcount, overflow, bigmax, bigflag;
   __shared__ int wtot[G / kWave];
   const int tid = threadIdx.x;
   const int TW = T / 2;
@@ -432,7 +445,9 @@ __global__ __launch_bounds__(G) void k_num_bucket_blk(
   const int count = hdr->bin_count[bin];
   const int start = hdr->bin_start[bin];
   const int wpt = (TW + G - 1) / G;  // counter words per thread
-  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+  __shared__ int item;
+  for (int ri = block_next(&hdr->queue[bin], &item); ri < count;
+       ri = block_next(&hdr->queue[bin], &item)) {
     const int i = __builtin_amdgcn_readfirstlane(rows[start + ri]);
     const int rs = crp[i];
     const int nnz = crp[i + 1] - rs;
@@ -440,9 +455,11 @@ __global__ __launch_bounds__(G) void k_num_bucket_blk(
     if (tid == 0) {
       wcount = 0;
       overflow = 0;
+      bigmax = 0;
+      bigflag = 0;
     }
     __syncthreads();
-    BucketInsertB<VT> ins{cnt, ikey, ival, &wcount, mul, cap, false};
+    BucketInsertB<VT> ins{cnt, ikey, ival, &wcount, mul, cap, false, &bigflag};
     for_each_product<true, true, G, kUnroll, VT>(pr, i, true, tid, lS, st, ins);
     if (ins.over) overflow = 1;
     __syncthreads();
@@ -452,87 +469,100 @@ __global__ __launch_bounds__(G) void k_num_bucket_blk(
       __syncthreads();
       continue;
     }
-    // 1. bucket starts: exclusive scan of the 16-bit counters, in place
-    {
-      const int w0 = tid * wpt;
-      int loc = 0;
-      for (int j = 0; j < wpt; ++j) {
-        if (w0 + j < TW) {
-          const uint32_t wv = cnt[w0 + j];
-          loc += (int)(wv & 0xffffu) + (int)(wv >> 16);
-        }
-      }
-      int total;
-      int run = group_excl_scan<true, G>(loc, tid, wtot, total);
-      for (int j = 0; j < wpt; ++j) {
-        if (w0 + j < TW) {
-          const uint32_t wv = cnt[w0 + j];
-          const uint32_t lo = (uint32_t)run;
-          run += (int)(wv & 0xffffu);
-          const uint32_t hi = (uint32_t)run;
-          run += (int)(wv >> 16);
-          cnt[w0 + j] = lo | (hi << 16);
-        }
-      }
-    }
-    __syncthreads();
-    // 2. every product to start[bucket] + ticket
-    {
-      uint32_t kk[kBktJ];
-      VT vv[kBktJ];
-#pragma unroll
-      for (int j = 0; j < kBktJ; ++j) {
-        const int p = tid + j * G;
-        kk[j] = p < P ? ikey[p] : 0u;
-        vv[j] = p < P ? ival[p] : VT(0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < kBktJ; ++j) {
-        if (tid + j * G < P) {
-          const uint32_t c = kk[j] & 0xffffffu;
-          const int pos = bkt_start(cnt, mono_slot(c, mul)) + (int)(kk[j] >> 24);
-          ikey[pos] = c;
-          ival[pos] = vv[j];
-        }
-      }
-    }
-    __syncthreads();
     SPG_GLOBAL int32_t *cb = gpw(ccol) + rs;
     SPG_GLOBAL VT *vb = gpw(cval) + rs;
-    if (P == nnz) {
-      // no repeated column: bucket start + smaller columns in the bucket
-      for (int p = tid; p < P; p += G) {
-        const uint32_t c = ikey[p];
-        const uint32_t b = mono_slot(c, mul);
-        const int s0 = bkt_start(cnt, b);
-        const int s1 = b + 1 < (uint32_t)T ? bkt_start(cnt, b + 1) : P;
-        int r = s0;
-        for (int q = s0; q < s1; ++q) r += ikey[q] < c ? 1 : 0;
-        cb[r] = (int)c;
-        vb[r] = ival[p];
+    if (bigflag) {
+      // clustered columns: sort the staged products as a whole (tickets
+      // dropped), then the runs pass below
+      for (int p = tid; p < P; p += G) ikey[p] &= 0xffffffu;
+      __syncthreads();
+      lds_sort_pairs<true, G, VT>(ikey, ival, P, tid);
+    } else {
+      // 1. bucket starts: exclusive scan of the 16-bit counters, in place
+      {
+        const int w0 = tid * wpt;
+        int loc = 0, mx = 0;
+        for (int j = 0; j < wpt; ++j) {
+          if (w0 + j < TW) {
+            const uint32_t wv = cnt[w0 + j];
+            loc += (int)(wv & 0xffffu) + (int)(wv >> 16);
+            mx = max(mx, (int)max(wv & 0xffffu, wv >> 16));
+          }
+        }
+        if (mx > kBigBucket) atomicMax(&bigmax, mx);
+        int total;
+        int run = group_excl_scan<true, G>(loc, tid, wtot, total);
+        for (int j = 0; j < wpt; ++j) {
+          if (w0 + j < TW) {
+            const uint32_t wv = cnt[w0 + j];
+            const uint32_t lo = (uint32_t)run;
+            run += (int)(wv & 0xffffu);
+            const uint32_t hi = (uint32_t)run;
+            run += (int)(wv >> 16);
+            cnt[w0 + j] = lo | (hi << 16);
+          }
+        }
       }
       __syncthreads();
-      continue;
-    }
-    // 3. sort every bucket of two or more products by column
-    for (int b = tid; b < T; b += G) {
-      const int s0 = bkt_start(cnt, (uint32_t)b);
-      const int s1 = b + 1 < T ? bkt_start(cnt, (uint32_t)b + 1) : P;
-      for (int q = s0 + 1; q < s1; ++q) {
-        const uint32_t kq = ikey[q];
-        const VT vq = ival[q];
-        int r = q - 1;
-        while (r >= s0 && ikey[r] > kq) {
-          ikey[r + 1] = ikey[r];
-          ival[r + 1] = ival[r];
-          --r;
+      // 2. every product to start[bucket] + ticket
+      {
+        uint32_t kk[kBktJ];
+        VT vv[kBktJ];
+  #pragma unroll
+        for (int j = 0; j < kBktJ; ++j) {
+          const int p = tid + j * G;
+          kk[j] = p < P ? ikey[p] : 0u;
+          vv[j] = p < P ? ival[p] : VT(0);
         }
-        ikey[r + 1] = kq;
-        ival[r + 1] = vq;
+        __syncthreads();
+  #pragma unroll
+        for (int j = 0; j < kBktJ; ++j) {
+          if (tid + j * G < P) {
+            const uint32_t c = kk[j] & 0xffffffu;
+            const int pos = bkt_start(cnt, mono_slot(c, mul)) + (int)(kk[j] >> 24);
+            ikey[pos] = c;
+            ival[pos] = vv[j];
+          }
+        }
       }
+      __syncthreads();
+      const bool big = bigmax > kBigBucket;
+      if (P == nnz && !big) {
+        // no repeated column: bucket start + smaller columns in the bucket
+        for (int p = tid; p < P; p += G) {
+          const uint32_t c = ikey[p];
+          const uint32_t b = mono_slot(c, mul);
+          const int s0 = bkt_start(cnt, b);
+          const int s1 = b + 1 < (uint32_t)T ? bkt_start(cnt, b + 1) : P;
+          int r = s0;
+          for (int q = s0; q < s1; ++q) r += ikey[q] < c ? 1 : 0;
+          cb[r] = (int)c;
+          vb[r] = ival[p];
+        }
+        __syncthreads();
+        continue;
+      }
+      // 3. sort every bucket of two or more products by column, or the whole
+      //    row when a bucket is large
+      if (big) lds_sort_pairs<true, G, VT>(ikey, ival, P, tid);
+      for (int b = big ? T : tid; b < T; b += G) {
+        const int s0 = bkt_start(cnt, (uint32_t)b);
+        const int s1 = b + 1 < T ? bkt_start(cnt, (uint32_t)b + 1) : P;
+        for (int q = s0 + 1; q < s1; ++q) {
+          const uint32_t kq = ikey[q];
+          const VT vq = ival[q];
+          int r = q - 1;
+          while (r >= s0 && ikey[r] > kq) {
+            ikey[r + 1] = ikey[r];
+            ival[r + 1] = ival[r];
+            --r;
+          }
+          ikey[r + 1] = kq;
+          ival[r + 1] = vq;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
     // 4. each thread a contiguous range of positions: its run starts, one
     //    block scan, then the first of each run sums the run and writes it
     {
@@ -589,7 +619,9 @@ __global__ __launch_bounds__(1024) void k_num_fallback(const Problem *__restrict
   const int count = hdr->fallback_count;
   const int tid = threadIdx.x;
   Stage<VT> st{sb, sl, sa};
-  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+  __shared__ int item;
+  for (int ri = block_next(&hdr->queue[kQueueFallback], &item); ri < count;
+       ri = block_next(&hdr->queue[kQueueFallback], &item)) {
     const int i = fb_rows[ri];
     const int rs = crp[i];
     const int nnz = crp[i + 1] - rs;
@@ -637,26 +669,9 @@ __global__ __launch_bounds__(1024) void k_num_fallback(const Problem *__restrict
       __syncthreads();
     }
     if (tid == 0 && pre != nnz) atomicOr(&hdr->status, kStatInvalid);
-    for (int s = nnz + tid; s < P2; s += 1024) key[s] = 0x7fffffff;
     __syncthreads();
-    for (int kk = 2; kk <= P2; kk <<= 1) {
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int t = tid; t < P2 / 2; t += 1024) {
-          const int a = 2 * j * (t / j) + (t % j);
-          const int b = a + j;
-          const bool up = (a & kk) == 0;
-          const int ka = key[a], kb = key[b];
-          if ((ka > kb) == up) {
-            key[a] = kb;
-            key[b] = ka;
-            const VT va = val[a];
-            val[a] = val[b];
-            val[b] = va;
-          }
-        }
-        __syncthreads();
-      }
-    }
+    // columns are >= 0, so their bit patterns sort like the values
+    lds_sort_pairs<true, 1024, VT>(reinterpret_cast<uint32_t *>(key), val, nnz, tid);
     for (int t = tid; t < nnz; t += 1024) {
       ccol[rs + t] = key[t];
       cval[rs + t] = val[t];
@@ -673,7 +688,7 @@ __global__ __launch_bounds__(1024) void k_num_fallback(const Problem *__restrict
 template <bool LDSMAP>
 __global__ __launch_bounds__(1024) void k_sym_heavy(const Problem *__restrict__ pr,
                                                     const int32_t *__restrict__ rows,
-                                                    const WsHeader *__restrict__ hdr, int blo,
+                                                    WsHeader *__restrict__ hdr, int blo,
                                                     int lS, uint32_t *gbitmap, int32_t *cnt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int sb[1024], sl[1024];
@@ -686,7 +701,9 @@ __global__ __launch_bounds__(1024) void k_sym_heavy(const Problem *__restrict__ 
   const int count = hdr->bin_start[kHeavyBin + 1] - start;
   const int tid = threadIdx.x;
   Stage<float> st{sb, sl, nullptr};
-  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+  __shared__ int item;
+  for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
+       ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
     const int i = rows[start + ri];
     for (int w = tid; w < nw; w += 1024) map[w] = 0u;
     if (tid == 0) total = 0;
@@ -742,7 +759,9 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
     const int n4 = (int)(astride / VPV);
     for (int s = tid; s < n4; s += 1024) a4[s] = make_int4(0, 0, 0, 0);
   }
-  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+  __shared__ int item;
+  for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
+       ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
     const int i = rows[start + ri];
     for (int w = tid; w < nw; w += 1024) map[w] = 0u;
     // zeroed accumulator entries visible at device scope before the adds
@@ -888,7 +907,9 @@ __global__ __launch_bounds__(1024) void k_num_heavy_rng(
   Stage<VT> st{sb, sl, sa};
   for (int c = tid; c < W; c += 1024) panel[c] = VT(0);
   for (int w = tid; w < nwords; w += 1024) pmap[w] = 0u;
-  for (int ri = blockIdx.x; ri < count; ri += gridDim.x) {
+  __shared__ int item;
+  for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
+       ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
     const int i = rows[start + ri];
     const int rs = crp[i], re = crp[i + 1];
     // 1. products per range
@@ -1083,6 +1104,11 @@ hipError_t launch_symbolic_bins(const Problem *dpr, const BinPlan &bp, const WsL
   for (int b = 1; b <= bp.maxbin; ++b) {
     if (bp.known && bp.count[b] == 0) continue;
     int G = bp.lanes[b];
+    if (G == 1 && b == 1) {  // one thread per row
+      launch_sym_tiny(dpr, rows, hdr, b, bins_count(bp, b, b), bp.known, cnt, st);
+      continue;
+    }
+    if (G < 8) G = 8;
     if (G == kWave && sym_wave_lds_bytes(b) <= D.lds_per_block) {
       launch_sym_wave(dpr, rows, hdr, b, sub_log2(bp, b, G), bins_count(bp, b, b), cnt, st);
       continue;
@@ -1162,6 +1188,12 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
   for (int b = 1; b <= bp.maxbin; ++b) {
     if (bp.known && bp.count[b] == 0) continue;
     int G = bp.lanes[b];
+    if (G == 1 && b == 1) {  // one thread per row
+      launch_num_tiny(dpr, rows, hdr, b, bins_count(bp, b, b), bp.known, crp, ccol, cval,
+                      sizeof(VT) == 8, st);
+      continue;
+    }
+    if (G < 8) G = 8;
     if (G == kWave && num_wave_lds_bytes(b, sizeof(VT), pack) <= D.lds_per_block) {
       launch_num_wave(dpr, rows, hdr, b, sub_log2(bp, b, G), bins_count(bp, b, b),
                       mono_mul(bin_slots(b), bp.n), maxwin, pack, crp, ccol, cval,

@@ -105,6 +105,53 @@ __device__ __forceinline__ unsigned long long group_max_u64(unsigned long long v
   return t;
 }
 
+// Sorts key[0..P) ascending, carrying val, in LDS.  A bitonic network in
+// the form whose every compare-exchange moves the smaller key to the lower
+// position (each merge starts by comparing mirrored positions of its
+// block), so the positions past P behave as +infinity and are never
+// touched: no padding, any P.  The NT lanes t = 0..NT-1 of the group share
+// the pairs of each step; group_sync separates the steps.
+template <bool BLOCK, int NT, typename VT>
+__device__ void lds_sort_pairs(uint32_t *key, VT *val, int P, int t) {
+  int ln = 0;
+  while ((1 << ln) < P) ++ln;
+  const int half = (1 << ln) >> 1;
+  // block sizes and distances are powers of two: shifts and masks, no division
+  for (int lk = 1; lk <= ln; ++lk) {
+    const int k = 1 << lk;
+    for (int lj = lk - 1; lj >= 0; --lj) {
+      const int j = 1 << lj;
+      for (int q = t; q < half; q += NT) {
+        int a, b;
+        if (lj == lk - 1) {  // mirrored positions of a block of k
+          const int base = (q >> lj) << lk, off = q & (j - 1);
+          a = base + off;
+          b = base + k - 1 - off;
+        } else {  // half-cleaner at distance j
+          a = ((q >> lj) << (lj + 1)) + (q & (j - 1));
+          b = a + j;
+        }
+        if (b < P) {
+          const uint32_t ka = key[a], kb = key[b];
+          if (ka > kb) {
+            key[a] = kb;
+            key[b] = ka;
+            const VT va = val[a];
+            val[a] = val[b];
+            val[b] = va;
+          }
+        }
+      }
+      group_sync<BLOCK>();
+    }
+  }
+}
+
+// Buckets larger than this are not sorted one bucket per lane: the bucket
+// kernels sort the whole row instead (columns that cluster in a few
+// buckets, as in banded matrices).
+constexpr int kBigBucket = 16;
+
 // Key word of the numeric tables.  PACK (n <= 2^24): the column in the low
 // 24 bits and a rank counter biased by 128 in the top byte.
 template <bool PACK>

@@ -572,7 +572,11 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_bucket(
       n2 = n3;
       continue;
     }
-    // 1. bucket starts: exclusive scan of the 16-bit counters, in place
+    SPG_GLOBAL int32_t *cb = gpw(ccol) + cur.rs;
+    SPG_GLOBAL VT *vb = gpw(cval) + cur.rs;
+    // 1. bucket starts: exclusive scan of the 16-bit counters, in place;
+    //    the largest bucket decides how buckets are sorted
+    int bigmax = 0;
     {
       uint32_t wv[4];
       int loc = 0;
@@ -580,7 +584,10 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_bucket(
       for (int j = 0; j < 4; ++j) {
         wv[j] = j < wpl ? cnt[lane * wpl + j] : 0u;
         loc += (int)(wv[j] & 0xffffu) + (int)(wv[j] >> 16);
+        bigmax = max(bigmax, (int)max(wv[j] & 0xffffu, wv[j] >> 16));
       }
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) bigmax = max(bigmax, __shfl_xor(bigmax, off));
       int x = loc;
 #pragma unroll
       for (int off = 1; off < kWave; off <<= 1) {
@@ -620,9 +627,8 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_bucket(
         ival[pos] = vv[j];
       }
     }
-    SPG_GLOBAL int32_t *cb = gpw(ccol) + cur.rs;
-    SPG_GLOBAL VT *vb = gpw(cval) + cur.rs;
-    if (P == nnz) {
+    const bool big = bigmax > kBigBucket;
+    if (P == nnz && !big) {
       // no repeated column: a product's rank is its bucket's start plus the
       // number of smaller columns in the (small) bucket
       group_sync<false>();
@@ -645,8 +651,10 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_bucket(
       continue;
     }
     group_sync<false>();
-    // 3. sort every bucket of two or more products by column (insertion sort)
-    for (int b = lane; b < T; b += kWave) {
+    // 3. sort every bucket of two or more products by column (insertion sort
+    //    by one lane per bucket), or the whole row when a bucket is large
+    if (big) lds_sort_pairs<false, kWave, VT>(ikey, ival, P, lane);
+    for (int b = big ? T : lane; b < T; b += kWave) {
       const int s0 = (int)((cnt[b >> 1] >> ((b & 1) << 4)) & 0xffffu);
       const int s1 = b + 1 < T ? (int)((cnt[(b + 1) >> 1] >> (((b + 1) & 1) << 4)) & 0xffffu) : P;
       for (int q = s0 + 1; q < s1; ++q) {

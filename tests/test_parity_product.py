@@ -237,3 +237,17 @@ def test_uniform_2p20_fp32_full_size(B):
     got = gpu_product(B, A, Bm, np.float32)
     ref, S = oracle.spgemm(A.astype(np.float64), Bm.astype(np.float64), with_abs=True)
     assert_same_csr(got, ref, S, np.float32, what="2^20 uniform, every row")
+
+
+@pytest.mark.parametrize("d,dtype,kind", [(16, np.float64, "int"), (16, np.float32, "normal"),
+                                          (24, np.float32, "normal"), (48, np.float64, "int"),
+                                          (48, np.float32, "u01")])
+def test_banded_products(B, d, dtype, kind):
+    """Columns clustered on three diagonal bands (a structured matrix, as
+    the ones the paper permutes before multiplying): the products of a row
+    fall into a few buckets of the order-preserving bucketing, which the
+    bucket kernels then sort as a whole row.  Rows of 256, ~576 and ~2300
+    products: the one-wave kernel and two block-group sizes."""
+    n = 1 << 14
+    A = synth.banded_csr(n, d, [0, n // 8, -n // 8], 64, 51 + d, dtype, kind)
+    check(B, A, A, dtype, exact=(kind == "int"), what=f"banded d={d}")
