@@ -87,9 +87,11 @@ const DevInfo &dev_info() {
   d.num_maxbin_f32 = maxbin_for(d.lds_per_block, 1, 4);
   d.num_maxbin_f64 = maxbin_for(d.lds_per_block, 1, 8);
   d.mcl_maxbin = maxbin_for(d.lds_per_block, 2, 4);
+  d.split_bin = std::min(std::min(d.num_maxbin_f32, d.num_maxbin_f64) + 1, d.sym_maxbin + 1);
   (void)configure_lds_limits(d.lds_per_block);
   (void)configure_backward_lds(d.lds_per_block);
   (void)configure_mcl_lds(d.lds_per_block);
+  (void)configure_split_lds(d.lds_per_block);
   (void)configure_wave_lds(d.lds_per_block);
   (void)hipGetLastError();
   if (g_ndev == kMaxDevices) {  // more devices than the table: reuse the last entry
@@ -132,8 +134,59 @@ WsLayout ws_layout(int64_t m, int64_t n, int heavy_slots) {
   o = align256(o + (size_t)heavy_slots * (size_t)(std::max<int64_t>(n, 1) + 4) * 8);
   L.heavymap = o;  // used when a heavy row's bitmap does not fit in LDS
   o = align256(o + (size_t)heavy_slots * (size_t)((std::max<int64_t>(n, 1) + 31) / 32) * 4);
+  // Split heavy rows: the products are staged in the heavy accumulator
+  // region (a column and an FP64 value each, whatever the pass's dtype);
+  // every split row has more than 4096 products, which bounds the rows, and
+  // a row takes at most 3 segments and 1 item per 2048 products, plus one.
+  const size_t acc_bytes = (size_t)heavy_slots * (size_t)(std::max<int64_t>(n, 1) + 4) * 8;
+  const int64_t pcap = std::min<int64_t>((int64_t)(acc_bytes > 512 ? (acc_bytes - 512) / 12 : 0),
+                                         (int64_t)INT32_MAX - 1);
+  if (pcap >= 8192 && m > 0 && n > 0 && n <= ((int64_t)kSplitMaxRanges << kSplitLog2W)) {
+    const int64_t hmax = std::min<int64_t>(m, pcap / 4096 + 1);
+    L.split_F = (int)((n + (1 << kSplitLog2W) - 1) >> kSplitLog2W);
+    L.split_pcap = pcap;
+    L.split_hmax = (int)hmax;
+    L.split_segcap = (int)std::min<int64_t>(INT32_MAX / 2, 3 * pcap / 2048 + hmax);
+    L.split_itemcap = (int)std::min<int64_t>(INT32_MAX / 2, pcap / kSplitItem + hmax);
+    L.split_ctl = o;
+    o = align256(o + sizeof(SplitCtl));
+    L.split_rows = o;
+    o = align256(o + (size_t)hmax * sizeof(SplitRow));
+    L.split_fo = o;
+    o = align256(o + (size_t)hmax * (size_t)(L.split_F + 1) * 4);
+    L.split_cur = o;
+    o = align256(o + (size_t)hmax * (size_t)L.split_F * 4);
+    L.split_segs = o;
+    o = align256(o + (size_t)L.split_segcap * sizeof(SplitSeg));
+    L.split_items = o;
+    o = align256(o + (size_t)L.split_itemcap * sizeof(SplitItem));
+  }
   L.total = o;
   return L;
+}
+
+SplitCtl *split_ctl(const WsLayout &L, char *ws) {
+  return L.split_F > 0 ? reinterpret_cast<SplitCtl *>(ws + L.split_ctl) : nullptr;
+}
+
+SplitArgs split_args(const WsLayout &L, char *ws, int bin) {
+  SplitArgs a{};
+  a.bin = bin;
+  if (L.split_F <= 0) return a;
+  a.ctl = reinterpret_cast<SplitCtl *>(ws + L.split_ctl);
+  a.rows = reinterpret_cast<SplitRow *>(ws + L.split_rows);
+  a.fo = reinterpret_cast<int32_t *>(ws + L.split_fo);
+  a.cur = reinterpret_cast<int32_t *>(ws + L.split_cur);
+  a.segs = reinterpret_cast<SplitSeg *>(ws + L.split_segs);
+  a.items = reinterpret_cast<SplitItem *>(ws + L.split_items);
+  a.scol = reinterpret_cast<int32_t *>(ws + L.heavyacc);
+  a.sval = ws + L.heavyacc + (((size_t)L.split_pcap * 4 + 255) & ~(size_t)255);
+  a.F = L.split_F;
+  a.hmax = L.split_hmax;
+  a.segcap = L.split_segcap;
+  a.itemcap = L.split_itemcap;
+  a.pcap = L.split_pcap;
+  return a;
 }
 
 }  // namespace spg
@@ -273,7 +326,7 @@ int run_symbolic(spg_plan p, const Problem &pr, const spg_csr *A, const spg_csr 
   char *ws = p->ws;
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   Problem *dpr = reinterpret_cast<Problem *>(ws + L.problem);
-  hipError_t e = launch_setup(pr, dpr, hdr, true, clear, st);
+  hipError_t e = launch_setup(pr, dpr, hdr, true, clear, st, split_ctl(L, ws));
   if (e != hipSuccess) return SPG_ERR_HIP;
   if (p->flags & SPG_FLAG_VALIDATE) {
     // every later kernel exits once the status word is raised, so invalid
@@ -396,7 +449,7 @@ int run_numeric(spg_plan p, const Problem &pr, spg_dtype dtype, int32_t *C_col_i
   char *ws = p->ws;
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   Problem *dpr = reinterpret_cast<Problem *>(ws + p->L.problem);
-  hipError_t e = launch_setup(pr, dpr, hdr, false, false, st);
+  hipError_t e = launch_setup(pr, dpr, hdr, false, false, st, split_ctl(p->L, ws));
   if (e != hipSuccess) return SPG_ERR_HIP;
   const int maxbin = dtype == SPG_F64 ? D.num_maxbin_f64 : D.num_maxbin_f32;
   BinPlan bp = make_binplan(p, maxbin, p->counts_known, p->num_count);

@@ -17,7 +17,10 @@ namespace spg {
 // Setup: copy the problem into the workspace, clear the header's counters
 // (reset) and the status word (clear_status).  A status word that is not
 // cleared stays raised, so every later kernel of a captured sequence exits.
-__global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset, int clear_status) {
+// The split rows' reservations are cleared with the counters, their queue
+// cursors at every call.
+__global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset, int clear_status,
+                        SplitCtl *sc) {
   if (threadIdx.x == 0) *dst = pr;
   if (reset && threadIdx.x < kNB) {
     hdr->bin_count[threadIdx.x] = 0;
@@ -34,6 +37,15 @@ __global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset, int 
     hdr->long_count = 0;
   }
   if (threadIdx.x < kNB + 2) hdr->queue[threadIdx.x] = 0;
+  if (sc && threadIdx.x == 0) {
+    if (reset) {
+      sc->stage = 0;
+      sc->segs = 0;
+      sc->items = 0;
+    }
+    sc->q_scatter = 0;
+    sc->q_accum = 0;
+  }
 }
 
 // Optional validation of one CSR operand: row_ptr[0] == 0, non-decreasing,
@@ -393,9 +405,9 @@ BinEdges default_edges() {
 }
 
 hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool reset,
-                        bool clear_status, hipStream_t st) {
+                        bool clear_status, hipStream_t st, SplitCtl *sc) {
   hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, pr, dst, hdr, reset ? 1 : 0,
-                     clear_status ? 1 : 0);
+                     clear_status ? 1 : 0, sc);
   return hipGetLastError();
 }
 

@@ -82,6 +82,59 @@ struct WsHeader {
 };
 static_assert(sizeof(WsHeader) <= 256, "the operand descriptors follow at byte 256");
 
+// Heavy rows shared by many blocks.  The symbolic pass describes each such
+// row by ranges of 2^kSplitLog2W consecutive columns (products and distinct
+// columns per range) and cuts the ranges into segments: a range with more
+// than half of kSplitSeg products stands alone, the others are grouped so
+// that a segment holds at most kSplitSeg products.  The numeric pass first
+// scatters the row's products into per-range runs of a staging area, many
+// blocks per row (items of about kSplitItem products), then merges every
+// segment in LDS on its own, writing its part of the output row.
+constexpr int kSplitLog2W = 13;         // columns per range: 8192
+constexpr int kSplitMaxRanges = 1024;   // ranges per row: n <= 2^23
+constexpr int kSplitSeg = 4096;         // products of a sorted segment at most
+constexpr int kSplitItem = 2048;        // products per scatter item (target)
+
+// Counters of the split path: staging entries, segments and items reserved
+// by the symbolic pass (cleared with the header's counters), work-queue
+// cursors of the numeric pass (cleared at every pass).
+struct SplitCtl {
+  unsigned long long stage;
+  int32_t segs, items;
+  int32_t q_scatter, q_accum;
+};
+// One split row (index h in the row list from the first split bin): first
+// staging entry (-1: the row is not split), scatter items, products.
+struct SplitRow {
+  int32_t base, items, products, pad;
+};
+// A segment: ranges [f0, f1) of row h, its products at staging entries
+// base + pstart .. + pcount, its distinct columns at output positions
+// row_ptr[i] + dstart .. + dcount.
+struct SplitSeg {
+  int32_t h, f0, f1, pstart, pcount, dstart, dcount, pad;
+};
+// Scatter item j of row h: entries [j E / J, (j + 1) E / J) of the row's E
+// A entries (all parts in order), J = the row's items.  h < 0: unused.
+struct SplitItem {
+  int32_t h, j;
+};
+// Device view of the split region of a workspace.  F == 0: no split rows
+// (the symbolic pass only counts).
+struct SplitArgs {
+  SplitCtl *ctl;
+  SplitRow *rows;
+  int32_t *fo;   // per row: F + 1 exclusive prefix sums of the products per range
+  int32_t *cur;  // per row: F cursors of the scatter
+  SplitSeg *segs;
+  SplitItem *items;
+  int32_t *scol;  // staging: columns, then values (pcap entries each)
+  void *sval;
+  int32_t F, hmax, segcap, itemcap;
+  int64_t pcap;
+  int32_t bin;  // first bin of the split rows
+};
+
 constexpr int kQueueFallback = kNB;
 constexpr int kQueueHeavy = kNB + 1;
 

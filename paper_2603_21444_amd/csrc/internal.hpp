@@ -18,6 +18,7 @@ struct DevInfo {
   int num_maxbin_f32 = 10;       // largest LDS bin of the FP32 numeric pass
   int num_maxbin_f64 = 9;        // largest LDS bin of the FP64 numeric pass
   int mcl_maxbin = 10;           // largest LDS bin of the MCL iteration
+  int split_bin = 10;            // first bin of the rows split over many blocks
 };
 
 const DevInfo &dev_info();
@@ -26,6 +27,11 @@ const DevInfo &dev_info();
 struct WsLayout {
   size_t problem, binid, rows, fbrows, blockhist, scanpart, heavyacc, heavymap, total;
   int heavy_slots;
+  // split heavy rows (staging in the heavy accumulator region); split_F == 0: off
+  size_t split_ctl = 0, split_rows = 0, split_fo = 0, split_cur = 0, split_segs = 0,
+         split_items = 0;
+  int split_F = 0, split_hmax = 0, split_segcap = 0, split_itemcap = 0;
+  int64_t split_pcap = 0;
   size_t mcl_rabs = 0, mcl_slots = 0;  // MCL only: row sums of |x|, heavy-row slots
 };
 
@@ -57,7 +63,7 @@ struct BinPlan {
 };
 
 hipError_t launch_setup(const Problem &pr, Problem *dst, WsHeader *hdr, bool reset,
-                        bool clear_status, hipStream_t st);
+                        bool clear_status, hipStream_t st, SplitCtl *sc = nullptr);
 hipError_t launch_clear_status(WsHeader *hdr, hipStream_t st);
 hipError_t launch_validate(const int32_t *rp, const int32_t *col, int rows, int ncols,
                            int64_t nnz, WsHeader *hdr, hipStream_t st);
@@ -116,6 +122,21 @@ void launch_sym_tiny(const Problem *dpr, const int32_t *rows, const WsHeader *hd
 void launch_num_tiny(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin, int count,
                      bool known, const int32_t *crp, int32_t *ccol, void *cval, bool f64,
                      hipStream_t st);
+
+// Rows split over many blocks: the symbolic kernel of the rows from bin blo
+// on (counts, and the split description when sa.F > 0), and the numeric
+// pass of the split rows from bin blo on (rows handled by the LDS kernels
+// of the pass's dtype sit below blo).
+SplitArgs split_args(const WsLayout &L, char *ws, int bin);
+SplitCtl *split_ctl(const WsLayout &L, char *ws);  // NULL when the layout has no split region
+size_t split_sym_static_lds();
+hipError_t launch_sym_split(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int blo,
+                            int lS, bool lds_map, uint32_t *gbitmap, int grid, size_t lds,
+                            int32_t *cnt, const SplitArgs &sa, hipStream_t st);
+hipError_t launch_num_split(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int blo,
+                            int lS, const SplitArgs &sa, const int32_t *crp, int32_t *ccol,
+                            void *cval, bool f64, hipStream_t st);
+hipError_t configure_split_lds(size_t lds_max);
 
 // LDS bytes of one block of the symbolic / numeric kernel of bin b with G
 // lanes per row.

@@ -681,46 +681,16 @@ __global__ __launch_bounds__(1024) void k_num_fallback(const Problem *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Heavy rows (beyond every LDS table): a column bitmap (LDS when it fits,
-// else the slot's global bitmap), one block of 1024 threads per row; block b
-// owns slot b of the heavy scratch.
+// Heavy rows (beyond every LDS table) that are not split over many blocks:
+// one block of 1024 threads per row; block b owns slot b of the heavy
+// scratch.  The symbolic count of every heavy row is k_sym_split's.
 
-template <bool LDSMAP>
-__global__ __launch_bounds__(1024) void k_sym_heavy(const Problem *__restrict__ pr,
-                                                    const int32_t *__restrict__ rows,
-                                                    WsHeader *__restrict__ hdr, int blo,
-                                                    int lS, uint32_t *gbitmap, int32_t *cnt) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int sb[1024], sl[1024];
-  __shared__ int total;
-  const int n = pr->n;
-  const int nw = (n + 31) >> 5;
-  uint32_t *map = LDSMAP ? reinterpret_cast<uint32_t *>(smem_raw) : gbitmap + (size_t)blockIdx.x * nw;
-  if (hdr->status) return;
-  const int start = hdr->bin_start[blo];
-  const int count = hdr->bin_start[kHeavyBin + 1] - start;
-  const int tid = threadIdx.x;
-  Stage<float> st{sb, sl, nullptr};
-  __shared__ int item;
-  for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
-       ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
-    const int i = rows[start + ri];
-    for (int w = tid; w < nw; w += 1024) map[w] = 0u;
-    if (tid == 0) total = 0;
-    if (!LDSMAP) __threadfence();
-    __syncthreads();
-    int mine = 0;
-    auto fmark = each_product([&](int col, float) {
-      const uint32_t bit = 1u << (col & 31);
-      const uint32_t old = atomicOr(&map[col >> 5], bit);
-      mine += (old & bit) ? 0 : 1;
-    });
-    for_each_product<true, false, 1024, kUnroll, float>(pr, i, true, tid, lS, st, fmark);
-    if (mine) atomicAdd(&total, mine);
-    __syncthreads();
-    if (tid == 0) cnt[i] = total;
-    __syncthreads();
-  }
+// A heavy row that the split kernels take (row h of the split list, from
+// bin sa.bin on) is skipped here.
+__device__ __forceinline__ bool split_taken(const SplitArgs &sa, const WsHeader *hdr, int pos) {
+  if (sa.hmax <= 0) return false;
+  const int h = pos - hdr->bin_start[sa.bin];
+  return h >= 0 && h < sa.hmax && sa.rows[h].base >= 0;
 }
 
 // Numeric pass of heavy rows with the slot's dense accumulator in global
@@ -735,7 +705,7 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
                                                     uint32_t *gbitmap, VT *gacc,
                                                     const int32_t *__restrict__ crp,
                                                     int32_t *__restrict__ ccol,
-                                                    VT *__restrict__ cval) {
+                                                    VT *__restrict__ cval, SplitArgs spl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int wtot[16];
   __shared__ int sb[1024], sl[1024];
@@ -762,6 +732,7 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
   __shared__ int item;
   for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
        ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
+    if (split_taken(spl, hdr, start + ri)) continue;
     const int i = rows[start + ri];
     for (int w = tid; w < nw; w += 1024) map[w] = 0u;
     // zeroed accumulator entries visible at device scope before the adds
@@ -880,7 +851,8 @@ template <typename VT>
 __global__ __launch_bounds__(1024) void k_num_heavy_rng(
     const Problem *__restrict__ pr, const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
     int blo, int lS, int log2W, uint32_t *gbitmap, char *slots, size_t slot_bytes,
-    const int32_t *__restrict__ crp, int32_t *__restrict__ ccol, VT *__restrict__ cval) {
+    const int32_t *__restrict__ crp, int32_t *__restrict__ ccol, VT *__restrict__ cval,
+    SplitArgs spl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int W = 1 << log2W;
   VT *panel = reinterpret_cast<VT *>(smem_raw);                 // W values
@@ -910,6 +882,7 @@ __global__ __launch_bounds__(1024) void k_num_heavy_rng(
   __shared__ int item;
   for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
        ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
+    if (split_taken(spl, hdr, start + ri)) continue;
     const int i = rows[start + ri];
     const int rs = crp[i], re = crp[i + 1];
     // 1. products per range
@@ -1101,7 +1074,11 @@ hipError_t launch_symbolic_bins(const Problem *dpr, const BinPlan &bp, const WsL
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   const int32_t *rows = reinterpret_cast<const int32_t *>(ws + L.rows);
   const DevInfo &D = dev_info();
-  for (int b = 1; b <= bp.maxbin; ++b) {
+  // rows from the split bin on are counted (and described) by the split
+  // kernel; without a split region only the rows beyond every LDS bin are
+  const bool split = L.split_F > 0 && D.split_bin <= bp.maxbin + 1;
+  const int sbin = split ? D.split_bin : bp.maxbin + 1;
+  for (int b = 1; b < sbin; ++b) {
     if (bp.known && bp.count[b] == 0) continue;
     int G = bp.lanes[b];
     if (G == 1 && b == 1) {  // one thread per row
@@ -1131,18 +1108,16 @@ hipError_t launch_symbolic_bins(const Problem *dpr, const BinPlan &bp, const WsL
       default: sym_launch<1024>(dpr, rows, hdr, b, lS, lt, cnt, grid, lds, st); break;
     }
   }
-  const int hc = bins_count(bp, bp.maxbin + 1, kHeavyBin);
+  const int hc = bins_count(bp, sbin, kHeavyBin);
   if (hc != 0) {
     const int grid = grid_for(hc, 1, bp.heavy_slots);
     const int lS = sub_log2(bp, kHeavyBin, 1024);
-    if (lds_bitmap_fits(bp.n, 9 * 1024)) {
-      const size_t lds = (size_t)((bp.n + 31) >> 5) * 4;
-      hipLaunchKernelGGL(k_sym_heavy<true>, dim3(grid), dim3(1024), lds, st, dpr, rows, hdr,
-                         bp.maxbin + 1, lS, (uint32_t *)nullptr, cnt);
-    } else {
-      hipLaunchKernelGGL(k_sym_heavy<false>, dim3(grid), dim3(1024), 0, st, dpr, rows, hdr,
-                         bp.maxbin + 1, lS, reinterpret_cast<uint32_t *>(ws + L.heavymap), cnt);
-    }
+    SplitArgs sa = split_args(L, ws, sbin);
+    if (!split) sa.F = 0;
+    const bool ldsmap = lds_bitmap_fits(bp.n, split_sym_static_lds());
+    return launch_sym_split(dpr, rows, hdr, sbin, lS, ldsmap,
+                            reinterpret_cast<uint32_t *>(ws + L.heavymap), grid,
+                            ldsmap ? (size_t)((bp.n + 31) >> 5) * 4 : 0, cnt, sa, st);
   }
   return hipGetLastError();
 }
@@ -1250,21 +1225,31 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
     const int grid = grid_for(hc, 1, bp.heavy_slots);
     VT *acc = reinterpret_cast<VT *>(ws + L.heavyacc);
     const int lS = sub_log2(bp, kHeavyBin, 1024);
+    // rows split over many blocks first (their staging shares the heavy
+    // region with the one-block kernels below, which skip them)
+    SplitArgs sa{};
+    if (L.split_F > 0 && D.split_bin <= bp.maxbin + 1) {
+      sa = split_args(L, ws, D.split_bin);
+      hipError_t e = launch_num_split(dpr, reinterpret_cast<const int32_t *>(ws + L.rows), hdr,
+                                      bp.maxbin + 1, sub_log2(bp, kHeavyBin, kWave * 8), sa, crp,
+                                      ccol, cval, sizeof(VT) == 8, st);
+      if (e != hipSuccess) return e;
+    }
     const int log2W = sizeof(VT) == 4 ? 15 : 14;  // a 128 KiB panel
     const size_t rlds = ((size_t)sizeof(VT) << log2W) + ((size_t)4 << (log2W - 5));
     if ((int64_t)bp.n <= ((int64_t)kRngMax << log2W) &&
         rlds + heavy_rng_static_lds<VT>() <= D.lds_per_block) {
       hipLaunchKernelGGL((k_num_heavy_rng<VT>), dim3(grid), dim3(1024), rlds, st, dpr, rows, hdr,
                          bp.maxbin + 1, lS, log2W, reinterpret_cast<uint32_t *>(ws + L.heavymap),
-                         ws + L.heavyacc, heavy_slot_bytes(bp.n), crp, ccol, cval);
+                         ws + L.heavyacc, heavy_slot_bytes(bp.n), crp, ccol, cval, sa);
     } else if (lds_bitmap_fits(bp.n, 8 * 1024 + 1024 * sizeof(VT))) {
       const size_t lds = (size_t)((bp.n + 31) >> 5) * 4;
       hipLaunchKernelGGL((k_num_heavy<true, VT>), dim3(grid), dim3(1024), lds, st, dpr, rows,
-                         hdr, bp.maxbin + 1, lS, (uint32_t *)nullptr, acc, crp, ccol, cval);
+                         hdr, bp.maxbin + 1, lS, (uint32_t *)nullptr, acc, crp, ccol, cval, sa);
     } else {
       hipLaunchKernelGGL((k_num_heavy<false, VT>), dim3(grid), dim3(1024), 0, st, dpr, rows, hdr,
                          bp.maxbin + 1, lS, reinterpret_cast<uint32_t *>(ws + L.heavymap), acc,
-                         crp, ccol, cval);
+                         crp, ccol, cval, sa);
     }
   }
   return hipGetLastError();
@@ -1307,7 +1292,6 @@ hipError_t configure_lds_limits(size_t lds_max) {
       reinterpret_cast<const void *>(&k_sym_rows<256>),
       reinterpret_cast<const void *>(&k_sym_rows<512>),
       reinterpret_cast<const void *>(&k_sym_rows<1024>),
-      reinterpret_cast<const void *>(&k_sym_heavy<true>),
       reinterpret_cast<const void *>(&k_num_fallback<float>),
       reinterpret_cast<const void *>(&k_num_fallback<double>),
       reinterpret_cast<const void *>(&k_num_heavy<true, float>),

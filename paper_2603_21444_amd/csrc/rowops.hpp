@@ -262,17 +262,21 @@ struct Stage {
 // reads position (l mod S) of the B rows of entries l/S, l/S + G/S, ..., U
 // entries at a time so that U loads are in flight together, and consecutive
 // lanes read consecutive B entries.  Positions beyond S (B rows longer than
-// S) follow in a second loop.
+// S) follow in a second loop.  [elo, ehi) restricts the row to a window of
+// its entries (a row shared by several blocks).
 template <bool BLOCK, bool VALUES, int G, int U, typename VT, typename F>
 __device__ __forceinline__ void part_products(const Part &P, int i, bool active, int l, int lS,
                                               Stage<VT> st, F &f, int cfirst = 0,
-                                              int cstep = 1) {
+                                              int cstep = 1, int elo = 0,
+                                              int ehi = 0x7fffffff) {
   const SPG_GLOBAL int32_t *brp = gp(P.brp);
   const SPG_GLOBAL int32_t *bcol = gp(P.bcol);
   const SPG_GLOBAL VT *bval = gp(static_cast<const VT *>(P.bval));
   int as = 0, ae = 0;
   if (active) a_row(P, i, as, ae);
-  const int nA = ae - as;
+  if (ehi < ae - as) ae = as + ehi;
+  as += elo;
+  const int nA = ae > as ? ae - as : 0;
   for (int c0 = cfirst * G; c0 < nA; c0 += cstep * G) {
     const int e = c0 + l;
     if (e < nA) {
