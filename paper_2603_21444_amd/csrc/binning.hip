@@ -35,6 +35,7 @@ __global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset, int 
   if (threadIdx.x == 0) {
     hdr->fallback_count = 0;
     hdr->long_count = 0;
+    hdr->mid_count = 0;
   }
   if (threadIdx.x < kNB + 2) hdr->queue[threadIdx.x] = 0;
   if (sc && threadIdx.x == 0) {
@@ -45,6 +46,7 @@ __global__ void k_setup(Problem pr, Problem *dst, WsHeader *hdr, int reset, int 
     }
     sc->q_scatter = 0;
     sc->q_accum = 0;
+    sc->nuns = 0;
   }
 }
 
@@ -68,14 +70,14 @@ __global__ void k_validate(const int32_t *rp, const int32_t *col, int rows, int 
 // each selected B row with one 8-byte load: the rows of a wave's lanes lie
 // far apart, so every load instruction touches up to 64 cache lines and the
 // number of instructions is what costs.  Rows of more than kKeyWave A
-// entries (over all block products) are summed by the whole wave; rows of
-// more than kKeyLong entries (power-law hubs, which often sit next to each
-// other) are left to k_rowkey_long, one block per row, so that no wave sums
-// several of them one after another.  A row of a few hundred entries spread
-// over the K block products stays with its thread: eight gathers in flight
-// per thread keep it short, while the wave would take its rows one by one.
+// entries (over all block products) are deferred to k_rowkey_long: one wave
+// per row for up to kKeyLong entries, one block per row beyond.  Power-law
+// hubs sit next to each other (R-MAT puts them at the low row indices), so a
+// wave that summed its own long rows would take dozens of them one after
+// another while the rest of the grid idles; the deferred lists spread them
+// over all waves instead.
 constexpr int kBinBlock = 256;
-constexpr int kKeyWave = 256;
+constexpr int kKeyWave = 64;
 constexpr int kKeyLong = 2048;
 constexpr int kKeyLongBlock = 256;  // threads of k_rowkey_long
 constexpr uint8_t kBinDeferred = 0xff;
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   const int m = pr->m;
   const int i = blockIdx.x * kBinBlock + threadIdx.x;
   int64_t key = 0;
-  bool longrow = false, deferred = false;
+  bool deferred = false;
   if (i < m) {
     const int K = pr->K;
     int len = 0;
@@ -107,12 +109,12 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
       a_row(pr->part[k], i, as, ae);
       len += ae - as;
     }
-    longrow = len > kKeyWave;  // counted by the whole wave below
-    if (len > kKeyLong) {  // counted by k_rowkey_long
-      longrow = false;
+    if (len > kKeyWave) {  // counted by k_rowkey_long: long rows from the front, the others from the back
       deferred = true;
+      if (len > kKeyLong) longrows[atomicAdd(&hdr->long_count, 1)] = i;
+      else longrows[m - 1 - atomicAdd(&hdr->mid_count, 1)] = i;
     }
-    for (int k = 0; k < K && !longrow && !deferred; ++k) {
+    for (int k = 0; k < K && !deferred; ++k) {
       const Part &P = pr->part[k];
       int as, ae;
       a_row(P, i, as, ae);
@@ -133,35 +135,8 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
       for (; p < ae; ++p) key += brow_len(brp, acol[p]);
     }
   }
-  // rows with more than 64 entries: the wave sums their products together
-  uint64_t pend = __ballot(longrow);
-  while (pend) {
-    const int lead = __ffsll((unsigned long long)pend) - 1;
-    pend &= pend - 1;
-    const int ri = __shfl(i, lead);
-    int64_t part = 0;
-    for (int k = 0; k < pr->K; ++k) {
-      const Part &P = pr->part[k];
-      int as, ae;
-      a_row(P, ri, as, ae);
-      const SPG_GLOBAL int32_t *brp = gp(P.brp);
-      int p = as + lane_id();
-      for (; p + 3 * kWave < ae; p += 4 * kWave) {  // four gathers in flight per lane
-        int r[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, ri, p + u * kWave);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) part += brow_len(brp, r[u]);
-      }
-      for (; p < ae; p += kWave) part += brow_len(brp, a_entry_row(P, ri, p));
-    }
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if (lane_id() == lead) key = part;
-  }
   if (i < m && deferred) {
     binid[i] = kBinDeferred;
-    longrows[atomicAdd(&hdr->long_count, 1)] = i;
   } else if (i < m) {
     if (key == 0) cnt_zero[i] = 0;
     int b = bin_of(key, maxbin, edges);
@@ -182,9 +157,42 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   }
 }
 
-// Row keys of the rows k_rowkey deferred (more than kKeyLong A entries): one
-// block per row sums its B row lengths, then the row gets its bin, its place
-// in its block's histogram and its share of the product total.
+// The products of row i summed by NT threads (t = thread index among them),
+// four gathers in flight per thread; every thread holds a partial sum.
+template <int NT>
+__device__ __forceinline__ long long row_products(const Problem *__restrict__ pr, int i, int t) {
+  long long part = 0;
+  for (int k = 0; k < pr->K; ++k) {
+    const Part &P = pr->part[k];
+    int as, ae;
+    a_row(P, i, as, ae);
+    const SPG_GLOBAL int32_t *brp = gp(P.brp);
+    int p = as + t;
+    for (; p + 3 * NT < ae; p += 4 * NT) {
+      int r[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, i, p + u * NT);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) part += brow_len(brp, r[u]);
+    }
+    for (; p < ae; p += NT) part += brow_len(brp, a_entry_row(P, i, p));
+  }
+  return part;
+}
+
+// The deferred row of key `key`: its bin, its place in its block's
+// histogram (the histogram k_rowkey wrote), and the empty-row mark.
+__device__ __forceinline__ void place_row(int i, long long key, int maxbin, const BinEdges &edges,
+                                          uint8_t *binid, int32_t *blockhist, int nblk,
+                                          int32_t *cnt_zero) {
+  if (key == 0) cnt_zero[i] = 0;
+  const int b = bin_of(key, maxbin, edges);
+  binid[i] = (uint8_t)b;
+  atomicAdd(&blockhist[(int64_t)b * nblk + i / kBinBlock], 1);
+}
+
+// Row keys of the rows k_rowkey deferred: rows of more than kKeyLong A
+// entries one block per row, then the others one wave per row.
 __global__ __launch_bounds__(kKeyLongBlock) void k_rowkey_long(const Problem *__restrict__ pr, int maxbin,
                                                       BinEdges edges, uint8_t *binid,
                                                       int32_t *blockhist, int nblk,
@@ -195,25 +203,10 @@ __global__ __launch_bounds__(kKeyLongBlock) void k_rowkey_long(const Problem *__
   if (hdr->status) return;
   const int count = hdr->long_count;
   const int tid = threadIdx.x;
+  long long mine = 0;  // this wave's share of the product total
   for (int li = blockIdx.x; li < count; li += gridDim.x) {
     const int i = longrows[li];
-    long long part = 0;
-    for (int k = 0; k < pr->K; ++k) {
-      const Part &P = pr->part[k];
-      int as, ae;
-      a_row(P, i, as, ae);
-      const SPG_GLOBAL int32_t *brp = gp(P.brp);
-      constexpr int NT = kKeyLongBlock;
-      int p = as + tid;
-      for (; p + 3 * NT < ae; p += 4 * NT) {  // four gathers in flight per thread
-        int r[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = a_entry_row(P, i, p + u * NT);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) part += brow_len(brp, r[u]);
-      }
-      for (; p < ae; p += NT) part += brow_len(brp, a_entry_row(P, i, p));
-    }
+    long long part = row_products<kKeyLongBlock>(pr, i, tid);
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
     if (lane_id() == 0) wsum[tid / kWave] = part;
@@ -221,14 +214,25 @@ __global__ __launch_bounds__(kKeyLongBlock) void k_rowkey_long(const Problem *__
     if (tid == 0) {
       long long key = 0;
       for (int w = 0; w < kKeyLongBlock / kWave; ++w) key += wsum[w];
-      if (key == 0) cnt_zero[i] = 0;
-      const int b = bin_of(key, maxbin, edges);
-      binid[i] = (uint8_t)b;
-      atomicAdd(&blockhist[(int64_t)b * nblk + i / kBinBlock], 1);
-      atomicAdd((unsigned long long *)&hdr->products_total, (unsigned long long)key);
+      place_row(i, key, maxbin, edges, binid, blockhist, nblk, cnt_zero);
+      mine += key;
     }
     __syncthreads();
   }
+  const int m = pr->m;
+  const int mcount = hdr->mid_count;
+  constexpr int kWpb = kKeyLongBlock / kWave;
+  for (int li = blockIdx.x * kWpb + tid / kWave; li < mcount; li += gridDim.x * kWpb) {
+    const int i = longrows[m - 1 - li];
+    long long part = row_products<kWave>(pr, i, lane_id());
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (lane_id() == 0) {
+      place_row(i, part, maxbin, edges, binid, blockhist, nblk, cnt_zero);
+      mine += part;
+    }
+  }
+  if (lane_id() == 0 && mine) atomicAdd((unsigned long long *)&hdr->products_total, (unsigned long long)mine);
 }
 
 // Exclusive scan of one bin's per-block counts (block b of kNB; the counts

@@ -77,7 +77,8 @@ struct WsHeader {
   int32_t bin_count[kNB];
   int32_t bin_start[kNB + 1];
   int32_t fallback_count;
-  int32_t long_count;  // rows the row-key kernel leaves to k_rowkey_long
+  int32_t long_count;  // rows the row-key kernel leaves to k_rowkey_long: one block per row
+  int32_t mid_count;   // ... one wave per row
   int32_t queue[kNB + 2];  // work-queue cursors: per bin, fallback rows, heavy rows
 };
 static_assert(sizeof(WsHeader) <= 256, "the operand descriptors follow at byte 256");
@@ -102,22 +103,25 @@ struct SplitCtl {
   unsigned long long stage;
   int32_t segs, items;
   int32_t q_scatter, q_accum;
+  int32_t nuns;  // numeric pass: heavy rows left to the one-block kernels
 };
 // One split row (index h in the row list from the first split bin): first
-// staging entry (-1: the row is not split), scatter items, products.
+// staging entry (-1: the row is not split), scatter items, products, and
+// the row of C.
 struct SplitRow {
-  int32_t base, items, products, pad;
+  int32_t base, items, products, row;
 };
-// A segment: ranges [f0, f1) of row h, its products at staging entries
-// base + pstart .. + pcount, its distinct columns at output positions
-// row_ptr[i] + dstart .. + dcount.
+// A segment of split row h (-1: unused): columns [c0, c1), products at
+// staging entries stage .. stage + pcount, distinct columns dstart ..
+// dstart + dcount of the row; out = row_ptr[row] + dstart, filled in by the
+// numeric pass (-1: the row_ptr does not match).
 struct SplitSeg {
-  int32_t h, f0, f1, pstart, pcount, dstart, dcount, pad;
+  int32_t h, c0, c1, stage, pcount, dstart, dcount, out;
 };
-// Scatter item j of row h: entries [j E / J, (j + 1) E / J) of the row's E
-// A entries (all parts in order), J = the row's items.  h < 0: unused.
+// Scatter item of split row h (-1: unused), row i of C: the products of
+// the row's A entries [e0, e1) (all parts in order, numbered from 0).
 struct SplitItem {
-  int32_t h, j;
+  int32_t h, i, e0, e1;
 };
 // Device view of the split region of a workspace.  F == 0: no split rows
 // (the symbolic pass only counts).

@@ -134,8 +134,8 @@ hipError_t launch_sym_split(const Problem *dpr, const int32_t *rows, WsHeader *h
                             int lS, bool lds_map, uint32_t *gbitmap, int grid, size_t lds,
                             int32_t *cnt, const SplitArgs &sa, hipStream_t st);
 hipError_t launch_num_split(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int blo,
-                            int lS, const SplitArgs &sa, const int32_t *crp, int32_t *ccol,
-                            void *cval, bool f64, hipStream_t st);
+                            int lS, const SplitArgs &sa, int32_t *ulist, const int32_t *crp,
+                            int32_t *ccol, void *cval, bool f64, hipStream_t st);
 hipError_t configure_split_lds(size_t lds_max);
 
 // LDS bytes of one block of the symbolic / numeric kernel of bin b with G

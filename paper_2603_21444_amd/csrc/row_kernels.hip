@@ -685,12 +685,18 @@ __global__ __launch_bounds__(1024) void k_num_fallback(const Problem *__restrict
 // one block of 1024 threads per row; block b owns slot b of the heavy
 // scratch.  The symbolic count of every heavy row is k_sym_split's.
 
-// A heavy row that the split kernels take (row h of the split list, from
-// bin sa.bin on) is skipped here.
-__device__ __forceinline__ bool split_taken(const SplitArgs &sa, const WsHeader *hdr, int pos) {
-  if (sa.hmax <= 0) return false;
-  const int h = pos - hdr->bin_start[sa.bin];
-  return h >= 0 && h < sa.hmax && sa.rows[h].base >= 0;
+// With split rows, the rows left to these kernels are listed (ulist, count
+// at *ucount) by the split pass; otherwise they are the row list's rows of
+// bins blo and above.
+__device__ __forceinline__ const int32_t *heavy_list(const int32_t *rows, const WsHeader *hdr,
+                                                     int blo, const int32_t *ulist,
+                                                     const int32_t *ucount, int &count) {
+  if (ulist) {
+    count = *ucount;
+    return ulist;
+  }
+  count = hdr->bin_start[kHeavyBin + 1] - hdr->bin_start[blo];
+  return rows + hdr->bin_start[blo];
 }
 
 // Numeric pass of heavy rows with the slot's dense accumulator in global
@@ -705,7 +711,8 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
                                                     uint32_t *gbitmap, VT *gacc,
                                                     const int32_t *__restrict__ crp,
                                                     int32_t *__restrict__ ccol,
-                                                    VT *__restrict__ cval, SplitArgs spl) {
+                                                    VT *__restrict__ cval,
+                                                    const int32_t *ulist, const int32_t *ucount) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int wtot[16];
   __shared__ int sb[1024], sl[1024];
@@ -717,8 +724,8 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
   const size_t astride = (size_t)(n + VPV - 1) / VPV * VPV;  // 16-byte aligned slots
   VT *acc = gacc + (size_t)blockIdx.x * astride;
   if (hdr->status) return;
-  const int start = hdr->bin_start[blo];
-  const int count = hdr->bin_start[kHeavyBin + 1] - start;
+  int count;
+  const int32_t *list = heavy_list(rows, hdr, blo, ulist, ucount, count);
   const int tid = threadIdx.x;
   Stage<VT> st{sb, sl, sa};
   if ((int)blockIdx.x >= count) return;
@@ -732,8 +739,7 @@ __global__ __launch_bounds__(1024) void k_num_heavy(const Problem *__restrict__ 
   __shared__ int item;
   for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
        ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
-    if (split_taken(spl, hdr, start + ri)) continue;
-    const int i = rows[start + ri];
+    const int i = list[ri];
     for (int w = tid; w < nw; w += 1024) map[w] = 0u;
     // zeroed accumulator entries visible at device scope before the adds
     __threadfence();
@@ -852,7 +858,7 @@ __global__ __launch_bounds__(1024) void k_num_heavy_rng(
     const Problem *__restrict__ pr, const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
     int blo, int lS, int log2W, uint32_t *gbitmap, char *slots, size_t slot_bytes,
     const int32_t *__restrict__ crp, int32_t *__restrict__ ccol, VT *__restrict__ cval,
-    SplitArgs spl) {
+    const int32_t *ulist, const int32_t *ucount) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int W = 1 << log2W;
   VT *panel = reinterpret_cast<VT *>(smem_raw);                 // W values
@@ -865,8 +871,8 @@ __global__ __launch_bounds__(1024) void k_num_heavy_rng(
   __shared__ VT sa[1024];
   if (hdr->status) return;
   const int n = pr->n;
-  const int start = hdr->bin_start[blo];
-  const int count = hdr->bin_start[kHeavyBin + 1] - start;
+  int count;
+  const int32_t *list = heavy_list(rows, hdr, blo, ulist, ucount, count);
   const int tid = threadIdx.x;
   if ((int)blockIdx.x >= count) return;
   char *slot = slots + (size_t)blockIdx.x * slot_bytes;
@@ -882,8 +888,7 @@ __global__ __launch_bounds__(1024) void k_num_heavy_rng(
   __shared__ int item;
   for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
        ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
-    if (split_taken(spl, hdr, start + ri)) continue;
-    const int i = rows[start + ri];
+    const int i = list[ri];
     const int rs = crp[i], re = crp[i + 1];
     // 1. products per range
     for (int r = tid; r < R; r += 1024) rpos[r] = 0;
@@ -1227,13 +1232,17 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
     const int lS = sub_log2(bp, kHeavyBin, 1024);
     // rows split over many blocks first (their staging shares the heavy
     // region with the one-block kernels below, which skip them)
-    SplitArgs sa{};
+    const int32_t *ulist = nullptr, *ucount = nullptr;
     if (L.split_F > 0 && D.split_bin <= bp.maxbin + 1) {
-      sa = split_args(L, ws, D.split_bin);
-      hipError_t e = launch_num_split(dpr, reinterpret_cast<const int32_t *>(ws + L.rows), hdr,
-                                      bp.maxbin + 1, sub_log2(bp, kHeavyBin, kWave * 8), sa, crp,
-                                      ccol, cval, sizeof(VT) == 8, st);
+      const SplitArgs sa = split_args(L, ws, D.split_bin);
+      // the rows left over are listed where the fallback rows were (the
+      // fallback kernel above has finished with them)
+      hipError_t e = launch_num_split(dpr, rows, hdr, bp.maxbin + 1,
+                                      sub_log2(bp, kHeavyBin, kWave * 8), sa, fb, crp, ccol,
+                                      cval, sizeof(VT) == 8, st);
       if (e != hipSuccess) return e;
+      ulist = fb;
+      ucount = &sa.ctl->nuns;
     }
     const int log2W = sizeof(VT) == 4 ? 15 : 14;  // a 128 KiB panel
     const size_t rlds = ((size_t)sizeof(VT) << log2W) + ((size_t)4 << (log2W - 5));
@@ -1241,15 +1250,16 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
         rlds + heavy_rng_static_lds<VT>() <= D.lds_per_block) {
       hipLaunchKernelGGL((k_num_heavy_rng<VT>), dim3(grid), dim3(1024), rlds, st, dpr, rows, hdr,
                          bp.maxbin + 1, lS, log2W, reinterpret_cast<uint32_t *>(ws + L.heavymap),
-                         ws + L.heavyacc, heavy_slot_bytes(bp.n), crp, ccol, cval, sa);
+                         ws + L.heavyacc, heavy_slot_bytes(bp.n), crp, ccol, cval, ulist, ucount);
     } else if (lds_bitmap_fits(bp.n, 8 * 1024 + 1024 * sizeof(VT))) {
       const size_t lds = (size_t)((bp.n + 31) >> 5) * 4;
       hipLaunchKernelGGL((k_num_heavy<true, VT>), dim3(grid), dim3(1024), lds, st, dpr, rows,
-                         hdr, bp.maxbin + 1, lS, (uint32_t *)nullptr, acc, crp, ccol, cval, sa);
+                         hdr, bp.maxbin + 1, lS, (uint32_t *)nullptr, acc, crp, ccol, cval, ulist,
+                         ucount);
     } else {
       hipLaunchKernelGGL((k_num_heavy<false, VT>), dim3(grid), dim3(1024), 0, st, dpr, rows, hdr,
                          bp.maxbin + 1, lS, reinterpret_cast<uint32_t *>(ws + L.heavymap), acc,
-                         crp, ccol, cval, sa);
+                         crp, ccol, cval, ulist, ucount);
     }
   }
   return hipGetLastError();

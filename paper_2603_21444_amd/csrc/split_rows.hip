@@ -18,7 +18,7 @@
 //    output offset; or a single range with more products, summed in a
 //    dense LDS panel of 8192 columns.
 // A row the workspace cannot describe or stage stays with the one-block
-// heavy kernels, which skip the split rows.
+// heavy kernels, which take the list of such rows.
 #include "internal.hpp"
 #include "rowops.hpp"
 
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
   __shared__ int pe[kSplitMaxRanges + 1], de[kSplitMaxRanges + 1];
   __shared__ int sstart[kSplitMaxRanges];
   __shared__ int wtot[16];
-  __shared__ int total, item, okflag, segbase, itembase;
+  __shared__ int total, item, okflag, segbase, itembase, stagebase, nentries;
   const int n = pr->n;
   const int nw = (n + 31) >> 5;
   uint32_t *map = LDSMAP ? reinterpret_cast<uint32_t *>(smem_raw) : gbitmap + (size_t)blockIdx.x * nw;
@@ -129,6 +129,13 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
     if (flag) sstart[sidx] = tid;
     const int J = (P + kSplitItem - 1) / kSplitItem;
     if (tid == 0) {
+      int E = 0;  // A entries of the row over all parts
+      for (int k = 0; k < pr->K; ++k) {
+        int as, ae;
+        a_row(pr->part[k], i, as, ae);
+        E += ae - as;
+      }
+      nentries = E;
       int ok = P > 0 && nseg > 0;
       long long b = -1;
       int sg = -1, ib = -1;
@@ -142,10 +149,11 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
         ok = sg <= sa.segcap - nseg && ib <= sa.itemcap - J;
       }
       okflag = ok;
+      stagebase = ok ? (int)b : -1;
       segbase = sg;
       itembase = ib;
       cnt[i] = total;
-      sa.rows[ri] = SplitRow{ok ? (int32_t)b : -1, J, P, 0};
+      sa.rows[ri] = SplitRow{ok ? (int32_t)b : -1, J, P, i};
     }
     __syncthreads();
     if (okflag) {
@@ -154,9 +162,13 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
       for (int s = tid; s < nseg; s += 1024) {
         const int f0 = sstart[s], f1 = s + 1 < nseg ? sstart[s + 1] : F;
         sa.segs[segbase + s] =
-            SplitSeg{ri, f0, f1, pe[f0], pe[f1] - pe[f0], de[f0], de[f1] - de[f0], 0};
+            SplitSeg{ri, f0 << kSplitLog2W, min(n, f1 << kSplitLog2W), stagebase + pe[f0],
+                     pe[f1] - pe[f0], de[f0], de[f1] - de[f0], -1};
       }
-      for (int j = tid; j < J; j += 1024) sa.items[itembase + j] = SplitItem{ri, j};
+      const int E = nentries;
+      for (int j = tid; j < J; j += 1024)
+        sa.items[itembase + j] =
+            SplitItem{ri, i, (int)((int64_t)j * E / J), (int)((int64_t)(j + 1) * E / J)};
     } else if (segbase >= 0) {
       // reserved but unusable entries are marked unused
       for (int s = tid; s < nseg && segbase + s < sa.segcap; s += 1024) sa.segs[segbase + s].h = -1;
@@ -166,15 +178,41 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Numeric, step 0: the scatter cursors of the split rows start at zero.
+// Numeric, step 0: the scatter cursors of the split rows start at zero, and
+// the heavy rows from bin blo on that are not split are listed for the
+// one-block kernels.
 
-__global__ void k_split_reset(const WsHeader *__restrict__ hdr, SplitArgs sa) {
+__global__ void k_split_prepare(const int32_t *__restrict__ rows, WsHeader *__restrict__ hdr,
+                                int blo, SplitArgs sa, const int32_t *__restrict__ crp,
+                                int32_t *__restrict__ ulist) {
   if (hdr->status) return;
-  const int rows = min(hdr->bin_start[kHeavyBin + 1] - hdr->bin_start[sa.bin], sa.hmax);
-  const int64_t total = (int64_t)rows * sa.F;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x)
+  const int sbin = hdr->bin_start[sa.bin];
+  const int nsplit = min(hdr->bin_start[kHeavyBin + 1] - sbin, sa.hmax);
+  const int64_t total = (int64_t)nsplit * sa.F;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = t0; t < total; t += step)
     if (sa.rows[t / sa.F].base >= 0) sa.cur[t] = 0;
+  const int start = hdr->bin_start[blo];
+  const int count = hdr->bin_start[kHeavyBin + 1] - start;
+  for (int64_t t = t0; t < count; t += step) {
+    const int h = start + (int)t - sbin;
+    if (!(h >= 0 && h < sa.hmax && sa.rows[h].base >= 0))
+      ulist[atomicAdd(&sa.ctl->nuns, 1)] = rows[start + t];
+  }
+  // output positions of the segments
+  const int nseg = min(sa.ctl->segs, sa.segcap);
+  for (int64_t t = t0; t < nseg; t += step) {
+    const SplitSeg sg = sa.segs[t];
+    if (sg.h < 0) continue;
+    const int i = sa.rows[sg.h].row;
+    int out = crp[i] + sg.dstart;
+    if (out + sg.dcount > crp[i + 1]) {  // the row_ptr does not match the description
+      atomicOr(&hdr->status, kStatInvalid);
+      out = -1;
+    }
+    sa.segs[t].out = out;
+  }
 }
 
 // Products of the item's window [e0, e1) of the row's A entries (all parts
@@ -284,17 +322,9 @@ __global__ __launch_bounds__(kScatterNT) void k_split_scatter(const Problem *__r
     const SplitItem it = sa.items[t];
     // unused, or a row of an LDS bin of this pass
     if (it.h < hlo || it.h >= sa.hmax) continue;
-    const SplitRow rr = sa.rows[it.h];
-    if (rr.base < 0 || it.j >= rr.items) continue;
-    const int i = rows[sbin + it.h];
-    int E = 0;
-    for (int k = 0; k < pr->K; ++k) {
-      int as, ae;
-      a_row(pr->part[k], i, as, ae);
-      E += ae - as;
-    }
-    const int e0 = (int)((int64_t)it.j * E / rr.items);
-    const int e1 = (int)((int64_t)(it.j + 1) * E / rr.items);
+    const int base = sa.rows[it.h].base;
+    if (base < 0) continue;
+    const int i = it.i, e0 = it.e0, e1 = it.e1;
     for (int c = tid; c < F; c += kScatterNT) lc[c] = 0;
     if (tid == 0) nb = 0;
     __syncthreads();
@@ -313,7 +343,7 @@ __global__ __launch_bounds__(kScatterNT) void k_split_scatter(const Problem *__r
           atomicOr(&hdr->status, kStatInvalid);
           lc[c] = INT32_MIN / 2;
         } else {
-          lc[c] = rr.base + fo[c] + p;
+          lc[c] = base + fo[c] + p;
         }
       }
     }
@@ -390,10 +420,16 @@ __device__ int merge_dense(const int32_t *__restrict__ scol, const VT *__restric
   return tot;
 }
 
+// Start of bucket b: the counters hold two 16-bit values per word.
+__device__ __forceinline__ int seg_bucket(const uint32_t *cnt, uint32_t b) {
+  return (int)((cnt[b >> 1] >> ((b & 1u) << 4)) & 0xffffu);
+}
+
 // At most kSplitSeg products over the columns [c0, c0 + span): placed into
-// T order-preserving buckets (bucket of column c: floor(c T / span)),
-// buckets sorted (or the whole segment when a bucket is large), runs of
-// equal columns summed.  Returns the distinct columns written.
+// T order-preserving buckets (bucket of column c: floor(c T / span), two
+// 16-bit counters per word), buckets sorted (or the whole segment when a
+// bucket is large), runs of equal columns summed.  Returns the distinct
+// columns written.
 template <typename VT>
 __device__ int merge_buckets(const int32_t *__restrict__ scol, const VT *__restrict__ sval, int P,
                              int c0, int span, int D, uint32_t *cnt, uint32_t *ikey, VT *ival,
@@ -403,11 +439,12 @@ __device__ int merge_buckets(const int32_t *__restrict__ scol, const VT *__restr
   const int tid = threadIdx.x;
   int T = 64;
   while (T < P) T <<= 1;
+  const int TW = T >> 1;
   const uint32_t mul = T >= span ? 0xffffffffu : (uint32_t)(((uint64_t)T << 32) / (uint64_t)span);
-  for (int b = tid; b < T; b += kAccumNT) cnt[b] = 0u;
+  for (int w = tid; w < TW; w += kAccumNT) cnt[w] = 0u;
   if (tid == 0) *bigmax = 0;
   __syncthreads();
-  uint32_t kc[J], kb[J], kt[J];
+  uint32_t kc[J], kbt[J];  // column; bucket | ticket << 16 (both below 2^16)
   VT kv[J];
   bool bad = false;
 #pragma unroll
@@ -423,38 +460,41 @@ __device__ int merge_buckets(const int32_t *__restrict__ scol, const VT *__restr
         bad = true;
         kc[j] = (uint32_t)span - 1;
       }
-      kb[j] = mono_slot(kc[j], mul);
-      kt[j] = atomicAdd(&cnt[kb[j]], 1u);
+      const uint32_t b = mono_slot(kc[j], mul);
+      const uint32_t sh = (b & 1u) << 4;
+      kbt[j] = b | (atomicAdd(&cnt[b >> 1], 1u << sh) >> sh) << 16;
     }
   }
   if (bad) atomicOr(&hdr->status, kStatInvalid);
   __syncthreads();
-  // bucket starts: exclusive scan, each thread a contiguous chunk of buckets
+  // bucket starts: exclusive scan, each thread a contiguous chunk of words
   {
-    const int per = (T + kAccumNT - 1) / kAccumNT;
-    const int b0 = tid * per;
+    const int per = (TW + kAccumNT - 1) / kAccumNT;
+    const int w0 = tid * per;
     int loc = 0, mx = 0;
     for (int q = 0; q < per; ++q)
-      if (b0 + q < T) {
-        const int v = (int)cnt[b0 + q];
-        loc += v;
-        mx = max(mx, v);
+      if (w0 + q < TW) {
+        const uint32_t v = cnt[w0 + q];
+        loc += (int)(v & 0xffffu) + (int)(v >> 16);
+        mx = max(mx, (int)max(v & 0xffffu, v >> 16));
       }
     if (mx > kBigBucket) atomicMax(bigmax, mx);
     int tot;
     int run = group_excl_scan<true, kAccumNT>(loc, tid, wtot, tot);
     for (int q = 0; q < per; ++q)
-      if (b0 + q < T) {
-        const int v = (int)cnt[b0 + q];
-        cnt[b0 + q] = (uint32_t)run;
-        run += v;
+      if (w0 + q < TW) {
+        const uint32_t v = cnt[w0 + q];
+        const uint32_t lo = (uint32_t)run;
+        run += (int)(v & 0xffffu);
+        cnt[w0 + q] = lo | ((uint32_t)run << 16);
+        run += (int)(v >> 16);
       }
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (tid + j * kAccumNT < P) {
-      const int pos = (int)(cnt[kb[j]] + kt[j]);
+      const int pos = seg_bucket(cnt, kbt[j] & 0xffffu) + (int)(kbt[j] >> 16);
       ikey[pos] = kc[j];
       ival[pos] = kv[j];
     }
@@ -466,8 +506,8 @@ __device__ int merge_buckets(const int32_t *__restrict__ scol, const VT *__restr
     for (int p = tid; p < P; p += kAccumNT) {
       const uint32_t c = ikey[p];
       const uint32_t b = mono_slot(c, mul);
-      const int s0 = (int)cnt[b];
-      const int s1 = (int)b + 1 < T ? (int)cnt[b + 1] : P;
+      const int s0 = seg_bucket(cnt, b);
+      const int s1 = (int)b + 1 < T ? seg_bucket(cnt, b + 1) : P;
       int r = s0;
       for (int q = s0; q < s1; ++q) r += ikey[q] < c ? 1 : 0;
       cb[r] = c0 + (int)c;
@@ -479,8 +519,8 @@ __device__ int merge_buckets(const int32_t *__restrict__ scol, const VT *__restr
     lds_sort_pairs<true, kAccumNT, VT>(ikey, ival, P, tid);
   } else {
     for (int b = tid; b < T; b += kAccumNT) {
-      const int s0 = (int)cnt[b];
-      const int s1 = b + 1 < T ? (int)cnt[b + 1] : P;
+      const int s0 = seg_bucket(cnt, (uint32_t)b);
+      const int s1 = b + 1 < T ? seg_bucket(cnt, (uint32_t)b + 1) : P;
       for (int q = s0 + 1; q < s1; ++q) {
         const uint32_t kq = ikey[q];
         const VT vq = ival[q];
@@ -519,24 +559,21 @@ __device__ int merge_buckets(const int32_t *__restrict__ scol, const VT *__restr
 }
 
 template <typename VT>
-__global__ __launch_bounds__(kAccumNT) void k_split_merge(const Problem *__restrict__ pr,
-                                                          const int32_t *__restrict__ rows,
-                                                          WsHeader *__restrict__ hdr, int blo,
+__global__ __launch_bounds__(kAccumNT, sizeof(VT) == 4 ? 8 : 4) void k_split_merge(WsHeader *__restrict__ hdr, int blo,
                                                           SplitArgs sa,
-                                                          const int32_t *__restrict__ crp,
                                                           int32_t *__restrict__ ccol,
                                                           VT *__restrict__ cval) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // bucket merge: counters | keys | values; dense merge: panel | bitmap
+  // bucket merge: counters (two per word) | keys | values; dense merge:
+  // panel | bitmap
   uint32_t *cnt = reinterpret_cast<uint32_t *>(smem_raw);
-  uint32_t *ikey = cnt + kSplitSeg;
+  uint32_t *ikey = cnt + kSplitSeg / 2;
   VT *ival = reinterpret_cast<VT *>(ikey + kSplitSeg);
   VT *panel = reinterpret_cast<VT *>(smem_raw);
   uint32_t *bm = reinterpret_cast<uint32_t *>(panel + (1 << kSplitLog2W));
   __shared__ int wtot[kAccumNT / kWave];
   __shared__ int item, bigmax;
   if (hdr->status) return;
-  const int n = pr->n;
   const int sbin = hdr->bin_start[sa.bin];
   const int hlo = hdr->bin_start[blo] - sbin;
   const int nseg = min(sa.ctl->segs, sa.segcap);
@@ -544,31 +581,22 @@ __global__ __launch_bounds__(kAccumNT) void k_split_merge(const Problem *__restr
   for (int t = block_next(&sa.ctl->q_accum, &item); t < nseg;
        t = block_next(&sa.ctl->q_accum, &item)) {
     const SplitSeg sg = sa.segs[t];
-    // unused, or a row of an LDS bin of this pass
-    if (sg.h < hlo || sg.h >= sa.hmax || sa.rows[sg.h].base < 0) continue;
+    // unused, a row of an LDS bin of this pass, or a row_ptr mismatch
+    if (sg.h < hlo || sg.out < 0) continue;
     if (sg.pcount == 0) {
       if (tid == 0 && sg.dcount != 0) atomicOr(&hdr->status, kStatInvalid);
       continue;
     }
-    const SplitRow rr = sa.rows[sg.h];
-    const int i = rows[sbin + sg.h];
-    const int o0 = crp[i] + sg.dstart;
-    if (o0 + sg.dcount > crp[i + 1]) {  // the row_ptr does not match the description
-      if (tid == 0) atomicOr(&hdr->status, kStatInvalid);
-      continue;
-    }
-    const int c0 = sg.f0 << kSplitLog2W;
-    const int c1 = min(n, sg.f1 << kSplitLog2W);
-    const size_t s0 = (size_t)rr.base + sg.pstart;
-    const int32_t *scol = sa.scol + s0;
-    const VT *sval = static_cast<const VT *>(sa.sval) + s0;
-    SPG_GLOBAL int32_t *cb = gpw(ccol) + o0;
-    SPG_GLOBAL VT *vb = gpw(cval) + o0;
+    const int32_t *scol = sa.scol + sg.stage;
+    const VT *sval = static_cast<const VT *>(sa.sval) + sg.stage;
+    SPG_GLOBAL int32_t *cb = gpw(ccol) + sg.out;
+    SPG_GLOBAL VT *vb = gpw(cval) + sg.out;
     const int got = sg.pcount > kSplitSeg
-                        ? merge_dense<VT>(scol, sval, sg.pcount, c0, sg.dcount, panel, bm, wtot,
-                                          cb, vb, hdr)
-                        : merge_buckets<VT>(scol, sval, sg.pcount, c0, c1 - c0, sg.dcount, cnt,
-                                            ikey, ival, wtot, &bigmax, cb, vb, hdr);
+                        ? merge_dense<VT>(scol, sval, sg.pcount, sg.c0, sg.dcount, panel, bm,
+                                          wtot, cb, vb, hdr)
+                        : merge_buckets<VT>(scol, sval, sg.pcount, sg.c0, sg.c1 - sg.c0,
+                                            sg.dcount, cnt, ikey, ival, wtot, &bigmax, cb, vb,
+                                            hdr);
     if (tid == 0 && got != sg.dcount) atomicOr(&hdr->status, kStatInvalid);
   }
 }
@@ -588,7 +616,7 @@ static size_t scatter_lds() {
 
 template <typename VT>
 static size_t merge_lds() {
-  const size_t buckets = (size_t)kSplitSeg * (8 + sizeof(VT));
+  const size_t buckets = (size_t)kSplitSeg * (6 + sizeof(VT));
   const size_t dense = ((size_t)sizeof(VT) << kSplitLog2W) + (size_t)kRangeWords * 4;
   return buckets > dense ? buckets : dense;
 }
@@ -615,10 +643,11 @@ hipError_t launch_sym_split(const Problem *dpr, const int32_t *rows, WsHeader *h
 
 template <typename VT>
 static void num_split(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int blo, int lS,
-                      const SplitArgs &sa, const int32_t *crp, int32_t *ccol, VT *cval,
-                      hipStream_t st) {
+                      const SplitArgs &sa, int32_t *ulist, const int32_t *crp, int32_t *ccol,
+                      VT *cval, hipStream_t st) {
   const DevInfo &D = dev_info();
-  hipLaunchKernelGGL(k_split_reset, dim3(D.cus * 4), dim3(256), 0, st, hdr, sa);
+  hipLaunchKernelGGL(k_split_prepare, dim3(D.cus * 4), dim3(256), 0, st, rows, hdr, blo, sa,
+                     crp, ulist);
   const size_t sl = scatter_lds<VT>();
   const int sg = D.cus * per_cu(sl, (size_t)kSplitMaxRanges * 4 + (size_t)kScatterNT * (8 + sizeof(VT)),
                                 kScatterNT);
@@ -626,16 +655,18 @@ static void num_split(const Problem *dpr, const int32_t *rows, WsHeader *hdr, in
                      lS, sa);
   const size_t ml = merge_lds<VT>();
   const int mg = D.cus * per_cu(ml, 256, kAccumNT);
-  hipLaunchKernelGGL(k_split_merge<VT>, dim3(mg), dim3(kAccumNT), ml, st, dpr, rows, hdr, blo, sa,
-                     crp, ccol, cval);
+  hipLaunchKernelGGL(k_split_merge<VT>, dim3(mg), dim3(kAccumNT), ml, st, hdr, blo, sa, ccol,
+                     cval);
 }
 
 hipError_t launch_num_split(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int blo,
-                            int lS, const SplitArgs &sa, const int32_t *crp, int32_t *ccol,
-                            void *cval, bool f64, hipStream_t st) {
+                            int lS, const SplitArgs &sa, int32_t *ulist, const int32_t *crp,
+                            int32_t *ccol, void *cval, bool f64, hipStream_t st) {
   if (sa.F <= 0) return hipSuccess;
-  if (f64) num_split<double>(dpr, rows, hdr, blo, lS, sa, crp, ccol, static_cast<double *>(cval), st);
-  else num_split<float>(dpr, rows, hdr, blo, lS, sa, crp, ccol, static_cast<float *>(cval), st);
+  if (f64)
+    num_split<double>(dpr, rows, hdr, blo, lS, sa, ulist, crp, ccol, static_cast<double *>(cval), st);
+  else
+    num_split<float>(dpr, rows, hdr, blo, lS, sa, ulist, crp, ccol, static_cast<float *>(cval), st);
   return hipGetLastError();
 }
 
