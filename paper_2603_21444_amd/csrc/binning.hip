@@ -70,14 +70,16 @@ __global__ void k_validate(const int32_t *rp, const int32_t *col, int rows, int 
 // each selected B row with one 8-byte load: the rows of a wave's lanes lie
 // far apart, so every load instruction touches up to 64 cache lines and the
 // number of instructions is what costs.  Rows of more than kKeyWave A
-// entries (over all block products) are deferred to k_rowkey_long: one wave
-// per row for up to kKeyLong entries, one block per row beyond.  Power-law
+// entries (over all block products) are deferred to k_rowkey_long: a group
+// of kKeyGroup lanes per row for up to kKeyLong entries, one block per row
+// beyond.  Power-law
 // hubs sit next to each other (R-MAT puts them at the low row indices), so a
 // wave that summed its own long rows would take dozens of them one after
 // another while the rest of the grid idles; the deferred lists spread them
 // over all waves instead.
 constexpr int kBinBlock = 256;
-constexpr int kKeyWave = 64;
+constexpr int kKeyWave = 256;
+constexpr int kKeyGroup = 16;  // lanes per deferred row of at most kKeyLong entries
 constexpr int kKeyLong = 2048;
 constexpr int kKeyLongBlock = 256;  // threads of k_rowkey_long
 constexpr uint8_t kBinDeferred = 0xff;
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
   const int m = pr->m;
   const int i = blockIdx.x * kBinBlock + threadIdx.x;
   int64_t key = 0;
-  bool deferred = false;
+  bool deferred = false, longrow = false;
   if (i < m) {
     const int K = pr->K;
     int len = 0;
@@ -109,11 +111,8 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
       a_row(pr->part[k], i, as, ae);
       len += ae - as;
     }
-    if (len > kKeyWave) {  // counted by k_rowkey_long: long rows from the front, the others from the back
-      deferred = true;
-      if (len > kKeyLong) longrows[atomicAdd(&hdr->long_count, 1)] = i;
-      else longrows[m - 1 - atomicAdd(&hdr->mid_count, 1)] = i;
-    }
+    deferred = len > kKeyWave;  // counted by k_rowkey_long
+    longrow = len > kKeyLong;
     for (int k = 0; k < K && !deferred; ++k) {
       const Part &P = pr->part[k];
       int as, ae;
@@ -134,6 +133,21 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
       }
       for (; p < ae; ++p) key += brow_len(brp, acol[p]);
     }
+  }
+  // deferred rows: long ones to the front of the list, the others to the
+  // back, one atomic per wave and list
+  {
+    const uint64_t lm = __ballot(deferred && longrow), mm = __ballot(deferred && !longrow);
+    const uint64_t lt = lane_id() == 0 ? 0ull : (~0ull >> (kWave - lane_id()));
+    int lb = 0, mb = 0;
+    if (lane_id() == 0) {
+      if (lm) lb = atomicAdd(&hdr->long_count, __popcll(lm));
+      if (mm) mb = atomicAdd(&hdr->mid_count, __popcll(mm));
+    }
+    lb = __shfl(lb, 0);
+    mb = __shfl(mb, 0);
+    if (deferred && longrow) longrows[lb + __popcll(lm & lt)] = i;
+    if (deferred && !longrow) longrows[m - 1 - (mb + __popcll(mm & lt))] = i;
   }
   if (i < m && deferred) {
     binid[i] = kBinDeferred;
@@ -158,7 +172,8 @@ __global__ __launch_bounds__(kBinBlock) void k_rowkey(const Problem *__restrict_
 }
 
 // The products of row i summed by NT threads (t = thread index among them),
-// four gathers in flight per thread; every thread holds a partial sum.
+// part by part, four gathers in flight per thread; every thread holds a
+// partial sum.
 template <int NT>
 __device__ __forceinline__ long long row_products(const Problem *__restrict__ pr, int i, int t) {
   long long part = 0;
@@ -192,7 +207,8 @@ __device__ __forceinline__ void place_row(int i, long long key, int maxbin, cons
 }
 
 // Row keys of the rows k_rowkey deferred: rows of more than kKeyLong A
-// entries one block per row, then the others one wave per row.
+// entries one block per row, then the others one group of kKeyGroup lanes
+// per row.
 __global__ __launch_bounds__(kKeyLongBlock) void k_rowkey_long(const Problem *__restrict__ pr, int maxbin,
                                                       BinEdges edges, uint8_t *binid,
                                                       int32_t *blockhist, int nblk,
@@ -203,7 +219,7 @@ __global__ __launch_bounds__(kKeyLongBlock) void k_rowkey_long(const Problem *__
   if (hdr->status) return;
   const int count = hdr->long_count;
   const int tid = threadIdx.x;
-  long long mine = 0;  // this wave's share of the product total
+  long long mine = 0;  // this lane's share of the product total
   for (int li = blockIdx.x; li < count; li += gridDim.x) {
     const int i = longrows[li];
     long long part = row_products<kKeyLongBlock>(pr, i, tid);
@@ -221,17 +237,24 @@ __global__ __launch_bounds__(kKeyLongBlock) void k_rowkey_long(const Problem *__
   }
   const int m = pr->m;
   const int mcount = hdr->mid_count;
-  constexpr int kWpb = kKeyLongBlock / kWave;
-  for (int li = blockIdx.x * kWpb + tid / kWave; li < mcount; li += gridDim.x * kWpb) {
-    const int i = longrows[m - 1 - li];
-    long long part = row_products<kWave>(pr, i, lane_id());
+  constexpr int kGpb = kKeyLongBlock / kKeyGroup;
+  const int g = tid / kKeyGroup, gl = tid % kKeyGroup;
+  // the loop bound is the same for the whole wave (its groups share the
+  // shuffles below), rows past the list end count nothing
+  const int first = blockIdx.x * kGpb + (tid / kWave) * (kWave / kKeyGroup);
+  for (int l0 = first; l0 < mcount; l0 += gridDim.x * kGpb) {
+    const int li = l0 + g % (kWave / kKeyGroup);
+    const int i = li < mcount ? longrows[m - 1 - li] : -1;
+    long long part = i >= 0 ? row_products<kKeyGroup>(pr, i, gl) : 0;
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if (lane_id() == 0) {
+    for (int off = kKeyGroup / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kKeyGroup);
+    if (gl == 0 && i >= 0) {
       place_row(i, part, maxbin, edges, binid, blockhist, nblk, cnt_zero);
       mine += part;
     }
   }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
   if (lane_id() == 0 && mine) atomicAdd((unsigned long long *)&hdr->products_total, (unsigned long long)mine);
 }
 
@@ -440,7 +463,7 @@ hipError_t launch_binning(const Problem *dpr, int m, int maxbin, const BinEdges 
   int32_t *longrows = reinterpret_cast<int32_t *>(ws + L.fbrows);  // free until the row kernels
   hipLaunchKernelGGL(k_rowkey, dim3(nblk), dim3(kBinBlock), 0, st, dpr, maxbin, edges,
                      binid, bh, cnt_zero, longrows, hdr);
-  hipLaunchKernelGGL(k_rowkey_long, dim3(dev_info().cus * 4), dim3(kKeyLongBlock), 0, st, dpr,
+  hipLaunchKernelGGL(k_rowkey_long, dim3(dev_info().cus * 8), dim3(kKeyLongBlock), 0, st, dpr,
                      maxbin, edges,
                      binid, bh, nblk, cnt_zero, longrows, hdr);
   hipLaunchKernelGGL(k_binscan, dim3(kNB), dim3(1024), 0, st, bh, nblk, hdr);
