@@ -97,6 +97,72 @@ def test_heavy_rows_beyond_the_staging_area(B, dtype):
     check(B, A, Bm, dtype, what="heavy beyond staging")
 
 
+def _band_rows(k, n, width, step, seed, dtype):
+    """k x n matrix whose row r holds `width` consecutive columns from
+    (r * step) mod n: products of nearby rows pile up on the same columns."""
+    rows = np.repeat(np.arange(k), width)
+    cols = ((rows * step) % n + np.tile(np.arange(width), k)) % n
+    order = np.lexsort((cols, rows))
+    vals = synth.draw_values(synth.rng_for(seed), cols.size, "normal", dtype)
+    return synth.HostCSR((k, n), np.arange(k + 1, dtype=np.int64) * width,
+                         cols[order].astype(np.int32), vals)
+
+
+def _rows_from(A, lists, seed, dtype):
+    """A with row i replaced by the columns lists[i] (for i in lists)."""
+    out_rows = []
+    rng = synth.rng_for(seed, 9)
+    for i in range(A.shape[0]):
+        if i in lists:
+            c = np.sort(np.asarray(lists[i], dtype=np.int32))
+            out_rows.append((c, synth.draw_values(rng, c.size, "normal", dtype)))
+        else:
+            out_rows.append(A.row(i))
+    ip = np.zeros(A.shape[0] + 1, dtype=np.int64)
+    np.cumsum([len(c) for c, _ in out_rows], out=ip[1:])
+    return synth.HostCSR(A.shape, ip, np.concatenate([c for c, _ in out_rows]).astype(np.int32),
+                         np.concatenate([v for _, v in out_rows]))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_split_rows_clustered_columns(B, dtype):
+    """Rows beyond the LDS tables whose products pile up on few columns:
+    column ranges with more products than a sorted segment (dense panel),
+    ranges alone with large buckets (whole-segment sort), grouped ranges,
+    and a long row over every range, in one launch."""
+    k, n = 20000, 60000
+    Bm = _band_rows(k, n, 48, 3, 31, dtype)
+    A = synth.varnnz_csr(400, k, 1, 30, 31, dtype, "normal")
+    lists = {
+        5: np.arange(2000, 2400),                    # 19200 products on ~1250 columns
+        17: np.arange(0, 20000, 10),                 # 96000 products over every range
+        40: np.concatenate([np.arange(s, s + 60) for s in (100, 5000, 9000, 15000)]),
+        41: np.concatenate([np.arange(s, s + 30) for s in range(0, 20000, 600)]),
+        60: np.arange(0, 20000, 100),                # ~1300 products per range: grouped
+    }
+    A = _rows_from(A, lists, 31, dtype)
+    check(B, A, Bm, dtype, what="split rows, clustered")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_split_rows_with_a_small_staging_area(B, dtype):
+    """One heavy slot: the staging area holds about n * 2/3 products, so the
+    first heavy rows to reserve it are split over many blocks and the others
+    stay with the one-block kernels, in the same launch."""
+    n = 60000
+    A = synth.varnnz_csr(300, 5000, 1, 40, 37, dtype, "normal", stream=0)
+    dense_rows = synth.uniform_csr(8, 5000, 1200, 37, dtype, "normal", stream=2)
+    A = _replace_rows(A, [3, 50, 77, 120, 150, 200, 250, 299], dense_rows)
+    Bm = synth.varnnz_csr(5000, n, 4, 32, 37, dtype, "normal", stream=1)
+    t = B.default_tuning()
+    t.heavy_slots = 1
+    plan = B.Plan(tuning=t)
+    got = B.spgemm(B.to_device(A, dtype=dtype), B.to_device(Bm, dtype=dtype), plan=plan).to_host()
+    f = lambda M: M.with_data(M.data.astype(dtype).astype(np.float64))
+    ref, S = oracle.spgemm(f(A), f(Bm), with_abs=True)
+    assert_same_csr(got, ref, S, dtype, what="split and one-block heavy rows")
+
+
 def _replace_rows(A, rows, R):
     """A with rows `rows` replaced by the rows of R (same column count)."""
     rows = list(rows)
