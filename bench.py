@@ -30,6 +30,7 @@ some):
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -287,23 +288,32 @@ def bench_backward(args):
     col, vals = plan.numeric([dA_], [dB_], rp, nnz)
     W = torch.from_numpy(synth.draw_values(synth.rng_for(SEED + 5, 9), nnz, "normal", np.float32)).cuda()
     dC = binding.DeviceCSR((n, n), rp, col, W)
-    for _ in range(max(1, args.warmup)):
-        plan.backward(dA_, dB_, dC)
-    torch.cuda.synchronize()
-    ev = _events(2)
-    s = torch.cuda.current_stream()
-    ev[0].record(s)
-    for _ in range(args.steps):
-        plan.backward(dA_, dB_, dC)
-    ev[1].record(s)
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    need = C.c_size_t(0)
+    binding.lib().spgemm_backward_deterministic_workspace_size(B.nnz, C.byref(need))
+    det_ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+
+    def timed(det):
+        for _ in range(max(1, args.warmup)):
+            plan.backward(dA_, dB_, dC, deterministic=det, det_workspace=det_ws)
+        torch.cuda.synchronize()
+        ev = _events(2)
+        s = torch.cuda.current_stream()
+        ev[0].record(s)
+        for _ in range(args.steps):
+            plan.backward(dA_, dB_, dC, deterministic=det, det_workspace=det_ws)
+        ev[1].record(s)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / args.steps
+
+    ms = timed(False)
+    det_ms = timed(True)
     _, products = plan.info()
     alg = csr_bytes(n, A.nnz, 4) + csr_bytes(n, B.nnz, 4) + 4 * (n + 1) + 8 * nnz + 4 * (A.nnz + B.nnz)
     gbs, frac = _roof(alg, ms)
     return {
         "workload": "dA = (W B^T) on S(A), dB = (A^T W) on S(B); A, B 2^18 x 2^18, 16 nnz/row, FP32",
         "products": int(products), "ms": round(ms, 4),
+        "deterministic_dB_ms": round(det_ms, 4),
         "gflops": round(4 * products / ms / 1e6, 2),
         "alg_GBs": gbs, "hbm_frac": frac, "algorithmic_bytes": int(alg),
     }

@@ -205,12 +205,33 @@ int spgemm_merge(spg_plan plan, int32_t K, const spg_csr *P, spg_dtype dtype,
  *              vals are dL/dC_ij.
  *   dA_vals    device [nnz(A)] or NULL (not computed), written.
  *   dB_vals    device [nnz(B)] or NULL, written (zeroed first, then
- *              accumulated with device atomics: the summation order of a
- *              dB entry is not fixed).
+ *              accumulated with device float atomics: the summation order
+ *              of a dB entry is not fixed; spgemm_backward_deterministic
+ *              below fixes the result).
  * Not in the paper; the definition is the derivative of the bilinear map
  * (A, B) -> A B at a fixed pattern. */
 int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg_csr *dC,
                     spg_dtype dtype, void *dA_vals, void *dB_vals, void *stream);
+
+/* The same backward with dB_vals the same bits on every run: each term
+ * a_ik * dC_ij (rounded in dtype, as in spgemm_backward) is added into a
+ * 128-bit fixed-point integer per B entry whose unit is 2^(E - 90), with
+ * 2^E above every |a_ik| * |dC_ij| (E from the largest |a| and |dC| of the
+ * call); integer addition does not depend on the order.  A term is
+ * truncated to the unit (an error below 2^-90 times the largest term of the
+ * call), then each sum is converted to dtype once.  dA_vals is computed as
+ * by spgemm_backward (each dA entry has one summing lane group: already
+ * deterministic).
+ *   workspace  device, 8-byte aligned, at least
+ *              spgemm_backward_deterministic_workspace_size(nnz(B)) bytes
+ *              (unused when dB_vals is NULL); the caller owns it.
+ * Non-finite values in A or dC raise SPG_ERR_INVALID in the plan's device
+ * status word, and dB_vals is then not written.  Capture-safe: every fill
+ * is a kernel, nothing is read back. */
+int spgemm_backward_deterministic_workspace_size(int64_t nnzB, size_t *bytes);
+int spgemm_backward_deterministic(spg_plan plan, const spg_csr *A, const spg_csr *B,
+                                  const spg_csr *dC, spg_dtype dtype, void *dA_vals,
+                                  void *dB_vals, void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Permutation B = P_r A P_c^T, i.e. B[row_perm[i], col_perm[j]] = A[i, j]

@@ -37,6 +37,7 @@ EXPORTS = [
     "spgemm_plan_create", "spgemm_plan_destroy", "spgemm_workspace_size",
     "spgemm_plan_status", "spgemm_plan_clear_status", "spgemm_plan_info", "spgemm_status_string",
     "spgemm_symbolic", "spgemm_symbolic_noalloc", "spgemm_numeric", "spgemm_merge", "spgemm_backward",
+    "spgemm_backward_deterministic", "spgemm_backward_deterministic_workspace_size",
     "spgemm_mcl_workspace_size", "spgemm_mcl_iteration", "spgemm_mcl_iteration_order",
     "spgemm_permute_workspace_size", "spgemm_permute",
     "spgemm_default_tuning", "spgemm_plan_set_tuning", "spgemm_plan_bins",
@@ -88,6 +89,8 @@ def lib():
             "spgemm_merge": (C.c_int, [P, I32, PC, C.c_int, P, C.POINTER(I64), I64, P, P, P,
                                        C.c_size_t, P]),
             "spgemm_backward": (C.c_int, [P, PC, PC, PC, C.c_int, P, P, P]),
+            "spgemm_backward_deterministic": (C.c_int, [P, PC, PC, PC, C.c_int, P, P, P, C.c_size_t, P]),
+            "spgemm_backward_deterministic_workspace_size": (C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),
             "spgemm_mcl_workspace_size": (C.c_int, [I32, I32, C.POINTER(C.c_size_t)]),
             "spgemm_mcl_iteration": (C.c_int, [P, PC, I32, C.c_float, I32, P, P, P, I64,
                                                C.POINTER(I64), P, C.c_size_t, P]),
@@ -323,16 +326,33 @@ class Plan:
         return col[:nnz], vals[:nnz]
 
     # ---- backward at fixed sparsity
-    def backward(self, A, B, dC, want_dA=True, want_dB=True, stream=None):
+    def backward(self, A, B, dC, want_dA=True, want_dB=True, stream=None,
+                 deterministic=False, det_workspace=None):
+        """dA, dB of C = A B at fixed sparsity; deterministic=True gives dB
+        the same bits on every run (fixed-point accumulation in a workspace
+        of its own: det_workspace, or allocated here)."""
         torch = _torch()
         dtype = A.vals.dtype
         dA = torch.empty(A.nnz, dtype=dtype, device=A.vals.device) if want_dA else None
         dB = torch.empty(B.nnz, dtype=dtype, device=B.vals.device) if want_dB else None
         a, b, c = A.spg(), B.spg(), dC.spg()
-        _check(lib().spgemm_backward(self.h, C.byref(a), C.byref(b), C.byref(c),
-                                     dtype_code(dtype), _ptr(dA) if (dA is not None and dA.numel()) else None,
-                                     _ptr(dB) if (dB is not None and dB.numel()) else None,
-                                     _stream(stream)), "spgemm_backward")
+        pa = _ptr(dA) if (dA is not None and dA.numel()) else None
+        pb = _ptr(dB) if (dB is not None and dB.numel()) else None
+        if not deterministic:
+            _check(lib().spgemm_backward(self.h, C.byref(a), C.byref(b), C.byref(c),
+                                         dtype_code(dtype), pa, pb, _stream(stream)),
+                   "spgemm_backward")
+            return dA, dB
+        need = C.c_size_t(0)
+        _check(lib().spgemm_backward_deterministic_workspace_size(B.nnz, C.byref(need)),
+               "spgemm_backward_deterministic_workspace_size")
+        ws = det_workspace
+        if ws is None or ws.numel() < need.value:
+            ws = torch.empty(need.value, dtype=torch.uint8, device=A.vals.device)
+        _check(lib().spgemm_backward_deterministic(self.h, C.byref(a), C.byref(b), C.byref(c),
+                                                   dtype_code(dtype), pa, pb, _ptr(ws),
+                                                   ws.numel(), _stream(stream)),
+               "spgemm_backward_deterministic")
         return dA, dB
 
 

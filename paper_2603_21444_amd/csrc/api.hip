@@ -458,6 +458,38 @@ int run_numeric(spg_plan p, const Problem &pr, spg_dtype dtype, int32_t *C_col_i
   return hip_status(e);
 }
 
+int run_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg_csr *dC,
+                 spg_dtype dtype, void *dA_vals, void *dB_vals, void *detws, size_t det_bytes,
+                 void *stream) {
+  (void)det_bytes;
+  if (!plan || !A || !B || !dC) return SPG_ERR_ARG;
+  if (!plan->sym_done || plan->merge_mode || plan->K != 1) return SPG_ERR_ARG;
+  if (dtype != SPG_F32 && dtype != SPG_F64) return SPG_ERR_ARG;
+  Problem pr;
+  int rc = fill_parts(pr, 1, A, B, false);
+  if (rc) return rc;
+  if (!same_operands(plan, 1, A, B)) return SPG_ERR_SHAPE;
+  rc = check_values(1, A, B, false);
+  if (rc) return rc;
+  if (dC->nrows != plan->m || dC->ncols != plan->n) return SPG_ERR_SHAPE;
+  if (plan->nnz >= 0 && dC->nnz != plan->nnz) return SPG_ERR_SHAPE;
+  if (!dC->row_ptr || (dC->nnz > 0 && (!dC->col_idx || !dC->vals))) return SPG_ERR_ARG;
+  if (!dA_vals && !dB_vals) return SPG_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DevInfo &D = dev_info();
+  char *ws = plan->ws;
+  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+  Problem *dpr = reinterpret_cast<Problem *>(ws + plan->L.problem);
+  hipError_t e = launch_setup(pr, dpr, hdr, false, false, st);
+  if (e != hipSuccess) return SPG_ERR_HIP;
+  const int maxbin = dtype == SPG_F64 ? D.num_maxbin_f64 : D.num_maxbin_f32;
+  BinPlan bp = make_binplan(plan, maxbin, plan->counts_known, plan->num_count);
+  e = launch_backward(dpr, bp, plan->L, ws, dC->row_ptr, dC->col_idx, dC->vals, dC->nnz, A->vals,
+                      dA_vals, A->nnz, dB_vals, B->nnz, dB_vals ? detws : nullptr, (int)dtype, st);
+  plan->stream = st;
+  return hip_status(e);
+}
+
 }  // namespace
 
 extern "C" {
@@ -667,32 +699,24 @@ int spgemm_merge(spg_plan plan, int32_t K, const spg_csr *P, spg_dtype dtype,
 
 int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg_csr *dC,
                     spg_dtype dtype, void *dA_vals, void *dB_vals, void *stream) {
-  if (!plan || !A || !B || !dC) return SPG_ERR_ARG;
-  if (!plan->sym_done || plan->merge_mode || plan->K != 1) return SPG_ERR_ARG;
-  if (dtype != SPG_F32 && dtype != SPG_F64) return SPG_ERR_ARG;
-  Problem pr;
-  int rc = fill_parts(pr, 1, A, B, false);
-  if (rc) return rc;
-  if (!same_operands(plan, 1, A, B)) return SPG_ERR_SHAPE;
-  rc = check_values(1, A, B, false);
-  if (rc) return rc;
-  if (dC->nrows != plan->m || dC->ncols != plan->n) return SPG_ERR_SHAPE;
-  if (plan->nnz >= 0 && dC->nnz != plan->nnz) return SPG_ERR_SHAPE;
-  if (!dC->row_ptr || (dC->nnz > 0 && (!dC->col_idx || !dC->vals))) return SPG_ERR_ARG;
-  if (!dA_vals && !dB_vals) return SPG_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const DevInfo &D = dev_info();
-  char *ws = plan->ws;
-  WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
-  Problem *dpr = reinterpret_cast<Problem *>(ws + plan->L.problem);
-  hipError_t e = launch_setup(pr, dpr, hdr, false, false, st);
-  if (e != hipSuccess) return SPG_ERR_HIP;
-  const int maxbin = dtype == SPG_F64 ? D.num_maxbin_f64 : D.num_maxbin_f32;
-  BinPlan bp = make_binplan(plan, maxbin, plan->counts_known, plan->num_count);
-  e = launch_backward(dpr, bp, plan->L, ws, dC->row_ptr, dC->col_idx, dC->vals, dA_vals,
-                      A->nnz, dB_vals, B->nnz, (int)dtype, st);
-  plan->stream = st;
-  return hip_status(e);
+  return run_backward(plan, A, B, dC, dtype, dA_vals, dB_vals, nullptr, 0, stream);
+}
+
+int spgemm_backward_deterministic_workspace_size(int64_t nnzB, size_t *bytes) {
+  if (!bytes || nnzB < 0) return SPG_ERR_ARG;
+  *bytes = det_workspace_bytes(nnzB);
+  return SPG_OK;
+}
+
+int spgemm_backward_deterministic(spg_plan plan, const spg_csr *A, const spg_csr *B,
+                                  const spg_csr *dC, spg_dtype dtype, void *dA_vals,
+                                  void *dB_vals, void *workspace, size_t ws_bytes, void *stream) {
+  if (!B) return SPG_ERR_ARG;
+  if (dB_vals) {
+    if (!workspace || ws_bytes < det_workspace_bytes(B->nnz)) return SPG_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) % 8) return SPG_ERR_ARG;
+  }
+  return run_backward(plan, A, B, dC, dtype, dA_vals, dB_vals, workspace, ws_bytes, stream);
 }
 
 int spgemm_permute_workspace_size(int32_t m, int32_t n, size_t *bytes) {

@@ -9,14 +9,58 @@
 // into an LDS hash keyed by column (rows beyond the LDS tables use a dense
 // row in the heavy-slot scratch instead).  Every product (p, q) looks up
 // w = W_i,col(q); dA_p collects w * b_q in an LDS accumulator of its A
-// entry, and a_p * w is added to dB_q with a device-scope atomic, so the
-// summation order of a dB entry is not fixed.
+// entry, and a_p * w is added to dB_q with a device-scope float atomic, so
+// the summation order of a dB entry is not fixed.
+//
+// Deterministic dB: the terms a_p * w (each rounded in the dtype, as in
+// the float path) are added into 128-bit fixed-point integers, one per B
+// entry, with 2^(E - 90) as the unit, where 2^E bounds every |a_p * w|
+// (E from the largest |a| and |w|, taken with order-free integer maxima).
+// Integer addition is associative, so every run gives the same bits; a
+// term is truncated to the unit (an error below 2^-90 of the largest term
+// of the whole product), and a sum of up to 2^31 terms still fits.  A last
+// pass converts the integers to the dtype.
 #include <vector>
 
 #include "internal.hpp"
 #include "rowops.hpp"
 
 namespace spg {
+
+// Deterministic dB: the fixed-point accumulators (lo: low 64 bits, hi: high
+// 64 bits, two's complement) and the exponent word (E, and the largest |a|
+// and |w| as bit patterns).  lo == NULL: float atomics.
+struct DetAcc {
+  unsigned long long *lo;
+  long long *hi;
+  unsigned long long *mx;  // [0] max |a| bits, [1] max |w| bits, [2] E (+ 2^32 when E is set)
+};
+
+__device__ __forceinline__ unsigned long long abs_bits(float v) {
+  return __float_as_uint(v) & 0x7fffffffu;
+}
+__device__ __forceinline__ unsigned long long abs_bits(double v) {
+  return (unsigned long long)__double_as_longlong(v) & 0x7fffffffffffffffull;
+}
+
+// Adds the term v (already rounded in the dtype) to accumulator q.
+template <typename VT>
+__device__ __forceinline__ void det_add(const DetAcc &d, int E, int64_t q, VT v) {
+  double x = ldexp((double)v, 90 - E);  // |x| < 2^91
+  const bool neg = x < 0.0;
+  x = fabs(x);
+  unsigned long long hm = (unsigned long long)floor(ldexp(x, -64));
+  unsigned long long lm = (unsigned long long)(x - ldexp((double)hm, 64));  // below 2^64, exact
+  unsigned long long lo = lm, hi = hm;
+  if (neg) {  // two's complement of the 128-bit magnitude
+    lo = ~lm + 1ull;
+    hi = ~hm + (lm == 0ull ? 1ull : 0ull);
+  }
+  if (lo == 0ull && hi == 0ull) return;
+  const unsigned long long old = atomicAdd(&d.lo[q], lo);
+  const unsigned long long carry = old + lo < old ? 1ull : 0ull;
+  if (hi + carry) atomicAdd(reinterpret_cast<unsigned long long *>(&d.hi[q]), hi + carry);
+}
 
 template <typename VT>
 __global__ void k_fill_zero(VT *p, int64_t n) {
@@ -81,7 +125,7 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
     const Problem *__restrict__ pr, const int32_t *__restrict__ rows,
     WsHeader *__restrict__ hdr, int bin, int lS, int log2T, const int32_t *__restrict__ crp,
     const int32_t *__restrict__ ccol, const VT *__restrict__ w, VT *__restrict__ dA,
-    VT *__restrict__ dB) {
+    VT *__restrict__ dB, DetAcc det) {
   using GM = BGeom<G>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int T = 1 << log2T;
@@ -98,6 +142,7 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
   const int count = hdr->bin_count[bin];
   const int start = hdr->bin_start[bin];
   const Part &P = pr->part[0];
+  const int E = det.lo ? (int)(int32_t)(uint32_t)det.mx[2] : 0;
   for (int ri = blockIdx.x * GM::R + rslot; ri < count; ri += gridDim.x * GM::R) {
     int i = rows[start + ri];
     if (G >= kWave) i = __builtin_amdgcn_readfirstlane(i);
@@ -132,7 +177,10 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
             h = (h + 1) & (T - 1);
           }
           const VT wij = wv[h];
-          if (dB) global_add(&dB[idx], sa[ee] * wij);
+          if (dB) {
+            if (det.lo) det_add<VT>(det, E, idx, sa[ee] * wij);
+            else global_add(&dB[idx], sa[ee] * wij);
+          }
           return wij * b;
         },
         [&](int p0, int nE) {
@@ -149,7 +197,8 @@ __global__ __launch_bounds__(1024) void k_bwd_heavy(const Problem *__restrict__ 
                                                     VT *gacc, const int32_t *__restrict__ crp,
                                                     const int32_t *__restrict__ ccol,
                                                     const VT *__restrict__ w,
-                                                    VT *__restrict__ dA, VT *__restrict__ dB) {
+                                                    VT *__restrict__ dA, VT *__restrict__ dB,
+                                                    DetAcc det) {
   __shared__ int sb[1024], sl[1024];
   __shared__ VT sa[1024], sd[1024];
   const int n = pr->n;
@@ -159,6 +208,7 @@ __global__ __launch_bounds__(1024) void k_bwd_heavy(const Problem *__restrict__ 
   const int count = hdr->bin_start[kHeavyBin + 1] - start;
   const int tid = threadIdx.x;
   const Part &P = pr->part[0];
+  const int E = det.lo ? (int)(int32_t)(uint32_t)det.mx[2] : 0;
   __shared__ int item;
   for (int ri = block_next(&hdr->queue[kQueueHeavy], &item); ri < count;
        ri = block_next(&hdr->queue[kQueueHeavy], &item)) {
@@ -171,7 +221,10 @@ __global__ __launch_bounds__(1024) void k_bwd_heavy(const Problem *__restrict__ 
         P, i, tid, lS, sb, sl, sa, sd,
         [&](int col, VT b, int idx, int ee) {
           const VT wij = dense[col];
-          if (dB) global_add(&dB[idx], sa[ee] * wij);
+          if (dB) {
+            if (det.lo) det_add<VT>(det, E, idx, sa[ee] * wij);
+            else global_add(&dB[idx], sa[ee] * wij);
+          }
           return wij * b;
         },
         [&](int p0, int nE) {
@@ -185,9 +238,73 @@ __global__ __launch_bounds__(1024) void k_bwd_heavy(const Problem *__restrict__ 
 template <int G, typename VT>
 static void bwd_launch(const Problem *dpr, const int32_t *rows, WsHeader *hdr, int bin, int lS,
                        int log2T, const int32_t *crp, const int32_t *ccol, const VT *w, VT *dA,
-                       VT *dB, int grid, size_t lds, hipStream_t st) {
+                       VT *dB, const DetAcc &det, int grid, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL((k_bwd_rows<G, VT>), dim3(grid), dim3(BGeom<G>::WG), lds, st, dpr, rows, hdr,
-                     bin, lS, log2T, crp, ccol, w, dA, dB);
+                     bin, lS, log2T, crp, ccol, w, dA, dB, det);
+}
+
+// Deterministic dB, before the product pass: the largest |a| and |w|
+// (integer maxima of the bit patterns of non-negative values, so no order
+// matters), then E with |a w| < 2^E for every term.
+template <typename VT>
+__global__ void k_det_absmax(const VT *__restrict__ a, int64_t na, const VT *__restrict__ w,
+                             int64_t nw, unsigned long long *mx) {
+  unsigned long long ma = 0, mw = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na; t += stride)
+    ma = max(ma, abs_bits(a[t]));
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nw; t += stride)
+    mw = max(mw, abs_bits(w[t]));
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    ma = max(ma, (unsigned long long)__shfl_xor(ma, off));
+    mw = max(mw, (unsigned long long)__shfl_xor(mw, off));
+  }
+  if (lane_id() == 0) {
+    if (ma) atomicMax(&mx[0], ma);
+    if (mw) atomicMax(&mx[1], mw);
+  }
+}
+
+template <typename VT>
+__global__ void k_det_exponent(unsigned long long *mx, WsHeader *hdr) {
+  if (threadIdx.x != 0) return;
+  VT ma, mw;
+  if (sizeof(VT) == 4) {
+    ma = (VT)__uint_as_float((uint32_t)mx[0]);
+    mw = (VT)__uint_as_float((uint32_t)mx[1]);
+  } else {
+    ma = (VT)__longlong_as_double((long long)mx[0]);
+    mw = (VT)__longlong_as_double((long long)mx[1]);
+  }
+  int E = 0;
+  if (!isfinite((double)ma) || !isfinite((double)mw)) {
+    atomicOr(&hdr->status, kStatInvalid);  // a fixed-point unit needs finite values
+  } else if (ma > VT(0) && mw > VT(0)) {
+    E = ilogb((double)ma) + ilogb((double)mw) + 2;  // |a| < 2^(ilogb+1), same for |w|
+  }
+  mx[2] = (unsigned long long)(uint32_t)E;
+}
+
+template <typename VT>
+__global__ void k_det_finish(const unsigned long long *__restrict__ lo,
+                             const long long *__restrict__ hi,
+                             const unsigned long long *__restrict__ mx, VT *__restrict__ dB,
+                             int64_t n, const WsHeader *__restrict__ hdr) {
+  if (hdr->status) return;
+  const int E = (int)(int32_t)(uint32_t)mx[2];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    unsigned long long l = lo[q], h = (unsigned long long)hi[q];
+    const bool neg = (long long)h < 0;
+    if (neg) {  // magnitude of the two's complement value
+      l = ~l + 1ull;
+      h = ~h + (l == 0ull ? 1ull : 0ull);
+    }
+    const double mag = ldexp((double)h, 64) + (double)l;
+    const double v = ldexp(neg ? -mag : mag, E - 90);
+    dB[q] = (VT)v;
+  }
 }
 
 size_t bwd_lds_bytes(int b, int G, size_t vbytes) {
@@ -199,13 +316,26 @@ size_t bwd_lds_bytes(int b, int G, size_t vbytes) {
 template <typename VT>
 static hipError_t backward_impl(const Problem *dpr, const BinPlan &bp, const WsLayout &L,
                                 char *ws, const int32_t *crp, const int32_t *ccol, const VT *w,
-                                VT *dA, int64_t nnzA, VT *dB, int64_t nnzB, hipStream_t st) {
+                                int64_t nnzC, const VT *aval, VT *dA, int64_t nnzA, VT *dB,
+                                int64_t nnzB, void *detws, hipStream_t st) {
   WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
   const int32_t *rows = reinterpret_cast<const int32_t *>(ws + L.rows);
   const DevInfo &D = dev_info();
+  DetAcc det{nullptr, nullptr, nullptr};
+  if (dB && detws) {
+    det.mx = static_cast<unsigned long long *>(detws);
+    det.lo = det.mx + 4;
+    det.hi = reinterpret_cast<long long *>(det.lo + nnzB);
+    // zero fills by kernel (capture-safe), then the exponent
+    hipLaunchKernelGGL(k_fill_zero<unsigned long long>, dim3(D.cus * 4), dim3(256), 0, st,
+                       det.mx, (int64_t)4 + 2 * nnzB);
+    hipLaunchKernelGGL(k_det_absmax<VT>, dim3(D.cus * 4), dim3(256), 0, st, aval, nnzA, w, nnzC,
+                       det.mx);
+    hipLaunchKernelGGL(k_det_exponent<VT>, dim3(1), dim3(64), 0, st, det.mx, hdr);
+  }
   if (dA && nnzA > 0)
     hipLaunchKernelGGL(k_fill_zero<VT>, dim3(D.cus * 4), dim3(256), 0, st, dA, nnzA);
-  if (dB && nnzB > 0)
+  if (dB && nnzB > 0 && !det.lo)
     hipLaunchKernelGGL(k_fill_zero<VT>, dim3(D.cus * 4), dim3(256), 0, st, dB, nnzB);
   for (int b = 1; b <= bp.maxbin; ++b) {
     if (bp.known && bp.count[b] == 0) continue;
@@ -225,7 +355,7 @@ static hipError_t backward_impl(const Problem *dpr, const BinPlan &bp, const WsL
     while ((1 << lS) < S) ++lS;
     switch (G) {
 #define SPG_BWD_CASE(g) \
-  case g: bwd_launch<g, VT>(dpr, rows, hdr, b, lS, lt, crp, ccol, w, dA, dB, grid, lds, st); break;
+  case g: bwd_launch<g, VT>(dpr, rows, hdr, b, lS, lt, crp, ccol, w, dA, dB, det, grid, lds, st); break;
       SPG_BWD_CASE(8)
       SPG_BWD_CASE(16)
       SPG_BWD_CASE(32)
@@ -233,7 +363,7 @@ static hipError_t backward_impl(const Problem *dpr, const BinPlan &bp, const WsL
       SPG_BWD_CASE(128)
       SPG_BWD_CASE(256)
       SPG_BWD_CASE(512)
-      default: bwd_launch<1024, VT>(dpr, rows, hdr, b, lS, lt, crp, ccol, w, dA, dB, grid, lds, st);
+      default: bwd_launch<1024, VT>(dpr, rows, hdr, b, lS, lt, crp, ccol, w, dA, dB, det, grid, lds, st);
 #undef SPG_BWD_CASE
     }
   }
@@ -250,21 +380,28 @@ static hipError_t backward_impl(const Problem *dpr, const BinPlan &bp, const WsL
     while ((1 << lS) < S) ++lS;
     hipLaunchKernelGGL(k_bwd_heavy<VT>, dim3(grid), dim3(1024), 0, st, dpr, rows, hdr,
                        bp.maxbin + 1, lS, reinterpret_cast<VT *>(ws + L.heavyacc), crp, ccol, w,
-                       dA, dB);
+                       dA, dB, det);
   }
+  if (det.lo && nnzB > 0)
+    hipLaunchKernelGGL(k_det_finish<VT>, dim3(D.cus * 4), dim3(256), 0, st, det.lo, det.hi, det.mx,
+                       dB, nnzB, hdr);
   return hipGetLastError();
 }
 
 hipError_t launch_backward(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
-                           const int32_t *crp, const int32_t *ccol, const void *w, void *dA,
-                           int64_t nnzA, void *dB, int64_t nnzB, int dtype, hipStream_t st) {
+                           const int32_t *crp, const int32_t *ccol, const void *w, int64_t nnzC,
+                           const void *aval, void *dA, int64_t nnzA, void *dB, int64_t nnzB,
+                           void *detws, int dtype, hipStream_t st) {
   if (dtype == SPG_F64)
-    return backward_impl<double>(dpr, bp, L, ws, crp, ccol, static_cast<const double *>(w),
-                                 static_cast<double *>(dA), nnzA, static_cast<double *>(dB), nnzB,
-                                 st);
-  return backward_impl<float>(dpr, bp, L, ws, crp, ccol, static_cast<const float *>(w),
-                              static_cast<float *>(dA), nnzA, static_cast<float *>(dB), nnzB, st);
+    return backward_impl<double>(dpr, bp, L, ws, crp, ccol, static_cast<const double *>(w), nnzC,
+                                 static_cast<const double *>(aval), static_cast<double *>(dA),
+                                 nnzA, static_cast<double *>(dB), nnzB, detws, st);
+  return backward_impl<float>(dpr, bp, L, ws, crp, ccol, static_cast<const float *>(w), nnzC,
+                              static_cast<const float *>(aval), static_cast<float *>(dA), nnzA,
+                              static_cast<float *>(dB), nnzB, detws, st);
 }
+
+size_t det_workspace_bytes(int64_t nnzB) { return (size_t)(4 + 2 * (nnzB > 0 ? nnzB : 0)) * 8; }
 
 hipError_t configure_backward_lds(size_t lds_max) {
   const void *ks[] = {

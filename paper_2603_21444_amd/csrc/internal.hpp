@@ -81,9 +81,13 @@ hipError_t launch_numeric(const Problem *dpr, const BinPlan &bp, const WsLayout 
                           hipStream_t st);
 hipError_t configure_lds_limits(size_t lds_max);
 
+// detws: NULL (dB by float atomics) or det_workspace_bytes(nnzB) bytes for
+// the deterministic dB.
 hipError_t launch_backward(const Problem *dpr, const BinPlan &bp, const WsLayout &L, char *ws,
-                           const int32_t *crp, const int32_t *ccol, const void *w, void *dA,
-                           int64_t nnzA, void *dB, int64_t nnzB, int dtype, hipStream_t st);
+                           const int32_t *crp, const int32_t *ccol, const void *w, int64_t nnzC,
+                           const void *aval, void *dA, int64_t nnzA, void *dB, int64_t nnzB,
+                           void *detws, int dtype, hipStream_t st);
+size_t det_workspace_bytes(int64_t nnzB);
 hipError_t configure_backward_lds(size_t lds_max);
 
 // rpre: exponent before the normalisation; rpost: 0 = renormalise after the

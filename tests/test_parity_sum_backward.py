@@ -183,6 +183,73 @@ def test_backward_heavy_and_empty_rows(B):
     assert np.all(np.abs(gB.cpu().numpy() - rB) <= 1e-12 * sB + 1e-300)
 
 
+def _backward_case(B, A, Bm, seed, dtype, kind="normal"):
+    import torch
+    dA_, dB_ = B.to_device(A), B.to_device(Bm)
+    plan = B.Plan()
+    rp, nnz = plan.symbolic([dA_], [dB_])
+    col, vals = plan.numeric([dA_], [dB_], rp, nnz)
+    Cg = B.DeviceCSR((A.shape[0], Bm.shape[1]), rp, col, vals).to_host()
+    W = synth.draw_values(synth.rng_for(seed, 9), nnz, kind, dtype)
+    dC = B.DeviceCSR((A.shape[0], Bm.shape[1]), rp, col, torch.from_numpy(W).cuda())
+    Cp = synth.HostCSR(Cg.shape, Cg.indptr, Cg.indices, None)
+    return plan, dA_, dB_, dC, Cp, W
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_backward_deterministic_dB(B, dtype):
+    """The deterministic backward: dB within tolerance of the oracle, the
+    same bits on repeated runs, dA identical to the float-atomic path."""
+    A = synth.uniform_csr(8192, 8192, 16, 15, dtype, "normal", stream=0)
+    Bm = synth.uniform_csr(8192, 8192, 16, 15, dtype, "normal", stream=1)
+    plan, dA_, dB_, dC, Cp, W = _backward_case(B, A, Bm, 15, dtype)
+    gA, gB = plan.backward(dA_, dB_, dC, deterministic=True)
+    gA2, gB2 = plan.backward(dA_, dB_, dC, deterministic=True)
+    fA, _ = plan.backward(dA_, dB_, dC)
+    assert plan.status() == B.SPG_OK
+    gA, gB, gA2, gB2, fA = (x.cpu().numpy() for x in (gA, gB, gA2, gB2, fA))
+    assert np.array_equal(gB.view(np.uint8), gB2.view(np.uint8))  # bit for bit
+    assert np.array_equal(gA.view(np.uint8), gA2.view(np.uint8))
+    assert np.array_equal(gA, fA)
+    rA, rB = oracle.backward(_f64(A), _f64(Bm), Cp, W.astype(np.float64))
+    sA, sB = _grad_scales(_f64(A), _f64(Bm), Cp, W.astype(np.float64))
+    t = tol_for(dtype)
+    assert np.all(np.abs(gB - rB) <= t * sB + 1e-300)
+    assert np.all(np.abs(gA - rA) <= t * sA + 1e-300)
+
+
+def test_backward_deterministic_exact_on_integers_with_heavy_rows(B):
+    """Small-integer values: every term and sum is exact in the fixed-point
+    units, so dB equals the oracle exactly, heavy rows and empty rows
+    included."""
+    A = synth.varnnz_csr(200, 3000, 0, 10, 18, np.float64, "int", stream=0)
+    dense_rows = synth.uniform_csr(3, 3000, 2000, 18, np.float64, "int", stream=2)
+    rows = [5, 60, 199]
+    out = [(dense_rows.row(rows.index(i)) if i in rows else A.row(i)) for i in range(200)]
+    ip = np.zeros(201, dtype=np.int64)
+    np.cumsum([len(c) for c, _ in out], out=ip[1:])
+    A = synth.HostCSR(A.shape, ip, np.concatenate([c for c, _ in out]).astype(np.int32),
+                      np.concatenate([v for _, v in out]))
+    Bm = synth.varnnz_csr(3000, 50000, 0, 24, 18, np.float64, "int", stream=1)
+    plan, dA_, dB_, dC, Cp, W = _backward_case(B, A, Bm, 18, np.float64, "int")
+    gA, gB = plan.backward(dA_, dB_, dC, deterministic=True)
+    assert plan.status() == B.SPG_OK
+    rA, rB = oracle.backward(A, Bm, Cp, W)
+    assert np.array_equal(gB.cpu().numpy(), rB)
+    assert np.array_equal(gA.cpu().numpy(), rA)
+
+
+def test_backward_deterministic_rejects_non_finite(B):
+    import torch
+    A = synth.uniform_csr(500, 500, 8, 19, np.float32, "normal", stream=0)
+    Bm = synth.uniform_csr(500, 500, 8, 19, np.float32, "normal", stream=1)
+    plan, dA_, dB_, dC, Cp, W = _backward_case(B, A, Bm, 19, np.float32)
+    W[3] = np.inf
+    dC = B.DeviceCSR(dC.shape, dC.row_ptr, dC.col_idx, torch.from_numpy(W).cuda())
+    plan.backward(dA_, dB_, dC, deterministic=True)
+    assert plan.status() == B.SPG_ERR_INVALID
+
+
 def test_autograd_function_and_euler_identity(B):
     """loss = <W, C>: autograd gradients equal the oracle's, and
     <A, dA> = L = <B, dB> (bilinearity)."""
