@@ -74,9 +74,13 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
     int mine = 0;
     auto fmark = each_product([&](int col, float) {
       const uint32_t bit = 1u << (col & 31);
-      const uint32_t old = atomicOr(&map[col >> 5], bit);
-      mine += (old & bit) ? 0 : 1;
-      if (rec) atomicAdd(&pe[col >> kSplitLog2W], 1);
+      if (rec) {  // distinct columns come from the popcounts below
+        atomicOr(&map[col >> 5], bit);
+        atomicAdd(&pe[col >> kSplitLog2W], 1);
+      } else {
+        const uint32_t old = atomicOr(&map[col >> 5], bit);
+        mine += (old & bit) ? 0 : 1;
+      }
     });
     for_each_product<true, false, 1024, kSplitSymUnroll, float>(pr, i, true, tid, lS, st, fmark);
     if (mine) atomicAdd(&total, mine);
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
       stagebase = ok ? (int)b : -1;
       segbase = sg;
       itembase = ib;
-      cnt[i] = total;
+      cnt[i] = D;
       sa.rows[ri] = SplitRow{ok ? (int32_t)b : -1, J, P, i};
     }
     __syncthreads();
