@@ -3,8 +3,10 @@
 C = A B at fixed sparsity: the patterns of A and B are constants, their
 values are the differentiable inputs, and the pattern of C is computed once
 (symbolic pass) and reused.  backward() runs spgemm_backward:
-dA = (dC B^T) on S(A), dB = (A^T dC) on S(B).  Every step runs in the HIP
-library; torch only holds memory and the autograd graph.
+dA = (dC B^T) on S(A), dB = (A^T dC) on S(B), or, for a pattern made with
+deterministic=True, spgemm_backward_deterministic (dB the same bits on
+every run).  Every step runs in the HIP library; torch only holds memory
+and the autograd graph.
 """
 from __future__ import annotations
 
@@ -37,15 +39,18 @@ class SpGEMMFunction(torch.autograd.Function):
         pat = ctx.pat
         dC = binding.DeviceCSR((A.shape[0], B.shape[1]), pat.row_ptr, pat.col_idx,
                                dc.contiguous().to(a_vals.dtype))
-        dA, dB = pat.plan.backward(A, B, dC, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        dA, dB = pat.plan.backward(A, B, dC, ctx.needs_input_grad[0], ctx.needs_input_grad[1],
+                                   deterministic=pat.deterministic)
         return dA, dB, None, None, None
 
 
 class SpGEMMPattern:
     """Symbolic pass of C = A B, done once for fixed patterns."""
 
-    def __init__(self, A_pat: binding.DeviceCSR, B_pat: binding.DeviceCSR, plan=None):
+    def __init__(self, A_pat: binding.DeviceCSR, B_pat: binding.DeviceCSR, plan=None,
+                 deterministic: bool = False):
         self.plan = plan or binding.Plan()
+        self.deterministic = deterministic
         self.row_ptr, self.nnz = self.plan.symbolic([A_pat], [B_pat])
         dev = A_pat.row_ptr.device
         self.col_tmp = torch.empty(max(self.nnz, 0), dtype=torch.int32, device=dev)

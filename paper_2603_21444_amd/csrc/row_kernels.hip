@@ -1238,7 +1238,7 @@ static hipError_t numeric_impl(const Problem *dpr, const BinPlan &bp, const WsLa
       // the rows left over are listed where the fallback rows were (the
       // fallback kernel above has finished with them)
       hipError_t e = launch_num_split(dpr, rows, hdr, bp.maxbin + 1,
-                                      sub_log2(bp, kHeavyBin, kWave * 8), sa, fb, crp, ccol,
+                                      sub_log2(bp, kHeavyBin, kWave * 4), sa, fb, crp, ccol,
                                       cval, sizeof(VT) == 8, st);
       if (e != hipSuccess) return e;
       ulist = fb;

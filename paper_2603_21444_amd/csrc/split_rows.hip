@@ -26,7 +26,7 @@ namespace spg {
 
 constexpr int kSplitSymUnroll = 4;
 constexpr int kSplitUnroll = 2;
-constexpr int kScatterNT = 512;         // threads of a scatter block
+constexpr int kScatterNT = 256;         // threads of a scatter block
 constexpr int kSplitBuf = 3072;         // products an item keeps in LDS
 constexpr int kAccumNT = 512;           // threads of a merge block
 constexpr int kRangeWords = (1 << kSplitLog2W) >> 5;  // bitmap words per range

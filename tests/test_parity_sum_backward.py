@@ -250,15 +250,17 @@ def test_backward_deterministic_rejects_non_finite(B):
     assert plan.status() == B.SPG_ERR_INVALID
 
 
-def test_autograd_function_and_euler_identity(B):
+@pytest.mark.parametrize("det", [False, True])
+def test_autograd_function_and_euler_identity(B, det):
     """loss = <W, C>: autograd gradients equal the oracle's, and
-    <A, dA> = L = <B, dB> (bilinearity)."""
+    <A, dA> = L = <B, dB> (bilinearity); with the deterministic backward a
+    second pass gives the same bits."""
     import torch
     from paper_2603_21444_amd.autograd import SpGEMMPattern, spgemm_values
     A = synth.uniform_csr(4096, 4096, 16, 12, np.float64, "normal", stream=0)
     Bm = synth.uniform_csr(4096, 4096, 16, 12, np.float64, "normal", stream=1)
     Ap, Bp = B.to_device(A), B.to_device(Bm)
-    pat = SpGEMMPattern(Ap, Bp)
+    pat = SpGEMMPattern(Ap, Bp, deterministic=det)
     a = Ap.vals.clone().requires_grad_(True)
     b = Bp.vals.clone().requires_grad_(True)
     c = spgemm_values(a, b, Ap, Bp, pat)
@@ -274,3 +276,7 @@ def test_autograd_function_and_euler_identity(B):
     sA, sB = _grad_scales(A, Bm, Cp, W.cpu().numpy())
     assert np.all(np.abs(a.grad.cpu().numpy() - rA) <= 1e-12 * sA + 1e-300)
     assert np.all(np.abs(b.grad.cpu().numpy() - rB) <= 1e-12 * sB + 1e-300)
+    if det:
+        b2 = Bp.vals.clone().requires_grad_(True)
+        (W * spgemm_values(a.detach(), b2, Ap, Bp, pat)).sum().backward()
+        assert torch.equal(b2.grad, b.grad)
