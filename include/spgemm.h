@@ -215,11 +215,13 @@ int spgemm_backward(spg_plan plan, const spg_csr *A, const spg_csr *B, const spg
 
 /* The same backward with dB_vals the same bits on every run: each term
  * a_ik * dC_ij (rounded in dtype, as in spgemm_backward) is added into a
- * 128-bit fixed-point integer per B entry whose unit is 2^(E - 90), with
- * 2^E above every |a_ik| * |dC_ij| (E from the largest |a| and |dC| of the
- * call); integer addition does not depend on the order.  A term is
- * truncated to the unit (an error below 2^-90 times the largest term of the
- * call), then each sum is converted to dtype once.  dA_vals is computed as
+ * fixed-point integer per B entry, with 2^E above every |a_ik| * |dC_ij|
+ * (E from the largest |a| and |dC| of the call); integer addition does not
+ * depend on the order.  FP64: 128-bit sums with the unit 2^(E - 90) (a term
+ * loses less than 2^-90 times the largest term of the call).  FP32: 64-bit
+ * sums with the unit 2^(E - 62 + L), 2^L >= the rows of A (a term loses
+ * less than 2^(L - 62) <= 2^-31 times the largest term).  Each sum is
+ * converted to dtype once.  dA_vals is computed as
  * by spgemm_backward (each dA entry has one summing lane group: already
  * deterministic).
  *   workspace  device, 8-byte aligned, at least

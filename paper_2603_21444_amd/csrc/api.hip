@@ -290,6 +290,7 @@ BinPlan make_binplan(spg_plan p, int maxbin, bool counts_known, const int *count
   }
   bp.maxbin = maxbin;
   bp.heavy_slots = p->L.heavy_slots;
+  bp.m = p->m;
   bp.n = p->n;
   bp.maxwin = p->tun.max_window;
   return bp;

@@ -13,13 +13,17 @@
 // the summation order of a dB entry is not fixed.
 //
 // Deterministic dB: the terms a_p * w (each rounded in the dtype, as in
-// the float path) are added into 128-bit fixed-point integers, one per B
-// entry, with 2^(E - 90) as the unit, where 2^E bounds every |a_p * w|
-// (E from the largest |a| and |w|, taken with order-free integer maxima).
-// Integer addition is associative, so every run gives the same bits; a
-// term is truncated to the unit (an error below 2^-90 of the largest term
-// of the whole product), and a sum of up to 2^31 terms still fits.  A last
-// pass converts the integers to the dtype.
+// the float path) are added into fixed-point integers, one per B entry,
+// where 2^E bounds every |a_p * w| (E from the largest |a| and |w|, taken
+// with order-free integer maxima).  FP64: 128-bit integers with the unit
+// 2^(E - 90), so a term loses less than 2^-90 of the largest term of the
+// whole product and a sum of up to 2^31 terms still fits.  FP32: 64-bit
+// integers with the unit 2^(E - 62 + L), 2^L >= the rows of A (the most
+// terms a dB entry can have), so a sum always fits and a term loses less
+// than 2^(L - 62) <= 2^-31 of the largest term, far below FP32 rounding;
+// one atomic per term, as in the float path.  Integer addition is
+// associative, so every run gives the same bits.  A last pass converts the
+// integers to the dtype.
 #include <vector>
 
 #include "internal.hpp"
@@ -28,12 +32,13 @@
 namespace spg {
 
 // Deterministic dB: the fixed-point accumulators (lo: low 64 bits, hi: high
-// 64 bits, two's complement) and the exponent word (E, and the largest |a|
-// and |w| as bit patterns).  lo == NULL: float atomics.
+// 64 bits of FP64 sums, two's complement) and the scale words (largest |a|
+// and |w| as bit patterns, then the shift S: a term v counts as v 2^S).
+// lo == NULL: float atomics.
 struct DetAcc {
   unsigned long long *lo;
   long long *hi;
-  unsigned long long *mx;  // [0] max |a| bits, [1] max |w| bits, [2] E (+ 2^32 when E is set)
+  unsigned long long *mx;  // [0] max |a| bits, [1] max |w| bits, [2] S
 };
 
 __device__ __forceinline__ unsigned long long abs_bits(float v) {
@@ -44,9 +49,12 @@ __device__ __forceinline__ unsigned long long abs_bits(double v) {
 }
 
 // Adds the term v (already rounded in the dtype) to accumulator q.
-template <typename VT>
-__device__ __forceinline__ void det_add(const DetAcc &d, int E, int64_t q, VT v) {
-  double x = ldexp((double)v, 90 - E);  // |x| < 2^91
+__device__ __forceinline__ void det_add(const DetAcc &d, int S, int64_t q, float v) {
+  const long long x = (long long)ldexp((double)v, S);  // |x| < 2^(62 - L)
+  if (x) atomicAdd(&d.lo[q], (unsigned long long)x);
+}
+__device__ __forceinline__ void det_add(const DetAcc &d, int S, int64_t q, double v) {
+  double x = ldexp(v, S);  // |x| < 2^91
   const bool neg = x < 0.0;
   x = fabs(x);
   unsigned long long hm = (unsigned long long)floor(ldexp(x, -64));
@@ -178,7 +186,7 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
           }
           const VT wij = wv[h];
           if (dB) {
-            if (det.lo) det_add<VT>(det, E, idx, sa[ee] * wij);
+            if (det.lo) det_add(det, E, idx, sa[ee] * wij);
             else global_add(&dB[idx], sa[ee] * wij);
           }
           return wij * b;
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(1024) void k_bwd_heavy(const Problem *__restrict__ 
         [&](int col, VT b, int idx, int ee) {
           const VT wij = dense[col];
           if (dB) {
-            if (det.lo) det_add<VT>(det, E, idx, sa[ee] * wij);
+            if (det.lo) det_add(det, E, idx, sa[ee] * wij);
             else global_add(&dB[idx], sa[ee] * wij);
           }
           return wij * b;
@@ -267,7 +275,7 @@ __global__ void k_det_absmax(const VT *__restrict__ a, int64_t na, const VT *__r
 }
 
 template <typename VT>
-__global__ void k_det_exponent(unsigned long long *mx, WsHeader *hdr) {
+__global__ void k_det_exponent(unsigned long long *mx, int m, WsHeader *hdr) {
   if (threadIdx.x != 0) return;
   VT ma, mw;
   if (sizeof(VT) == 4) {
@@ -283,7 +291,10 @@ __global__ void k_det_exponent(unsigned long long *mx, WsHeader *hdr) {
   } else if (ma > VT(0) && mw > VT(0)) {
     E = ilogb((double)ma) + ilogb((double)mw) + 2;  // |a| < 2^(ilogb+1), same for |w|
   }
-  mx[2] = (unsigned long long)(uint32_t)E;
+  int L = 1;
+  while (L < 31 && (1 << L) < m) ++L;
+  const int S = sizeof(VT) == 8 ? 90 - E : 62 - L - E;
+  mx[2] = (unsigned long long)(uint32_t)S;
 }
 
 template <typename VT>
@@ -292,9 +303,13 @@ __global__ void k_det_finish(const unsigned long long *__restrict__ lo,
                              const unsigned long long *__restrict__ mx, VT *__restrict__ dB,
                              int64_t n, const WsHeader *__restrict__ hdr) {
   if (hdr->status) return;
-  const int E = (int)(int32_t)(uint32_t)mx[2];
+  const int S = (int)(int32_t)(uint32_t)mx[2];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    if (sizeof(VT) == 4) {  // 64-bit sums
+      dB[q] = (VT)ldexp((double)(long long)lo[q], -S);
+      continue;
+    }
     unsigned long long l = lo[q], h = (unsigned long long)hi[q];
     const bool neg = (long long)h < 0;
     if (neg) {  // magnitude of the two's complement value
@@ -302,8 +317,7 @@ __global__ void k_det_finish(const unsigned long long *__restrict__ lo,
       h = ~h + (l == 0ull ? 1ull : 0ull);
     }
     const double mag = ldexp((double)h, 64) + (double)l;
-    const double v = ldexp(neg ? -mag : mag, E - 90);
-    dB[q] = (VT)v;
+    dB[q] = (VT)ldexp(neg ? -mag : mag, -S);
   }
 }
 
@@ -328,10 +342,10 @@ static hipError_t backward_impl(const Problem *dpr, const BinPlan &bp, const WsL
     det.hi = reinterpret_cast<long long *>(det.lo + nnzB);
     // zero fills by kernel (capture-safe), then the exponent
     hipLaunchKernelGGL(k_fill_zero<unsigned long long>, dim3(D.cus * 4), dim3(256), 0, st,
-                       det.mx, (int64_t)4 + 2 * nnzB);
+                       det.mx, (int64_t)4 + (sizeof(VT) == 8 ? 2 : 1) * nnzB);
     hipLaunchKernelGGL(k_det_absmax<VT>, dim3(D.cus * 4), dim3(256), 0, st, aval, nnzA, w, nnzC,
                        det.mx);
-    hipLaunchKernelGGL(k_det_exponent<VT>, dim3(1), dim3(64), 0, st, det.mx, hdr);
+    hipLaunchKernelGGL(k_det_exponent<VT>, dim3(1), dim3(64), 0, st, det.mx, bp.m, hdr);
   }
   if (dA && nnzA > 0)
     hipLaunchKernelGGL(k_fill_zero<VT>, dim3(D.cus * 4), dim3(256), 0, st, dA, nnzA);

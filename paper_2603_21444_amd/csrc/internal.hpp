@@ -58,6 +58,7 @@ struct BinPlan {
   int sub[kNB] = {0};       // lanes sharing one A entry's B row, per bin
   int maxbin = kMaxLdsBin;  // last LDS bin; bins above go to the heavy kernel
   int heavy_slots = 1;
+  int m = 0;  // rows
   int n = 0;
   int maxwin = 32;
 };
