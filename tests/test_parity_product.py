@@ -163,6 +163,18 @@ def test_split_rows_with_a_small_staging_area(B, dtype):
     assert_same_csr(got, ref, S, dtype, what="split and one-block heavy rows")
 
 
+@pytest.mark.parametrize("n", [100, 8192, 8193])
+def test_split_rows_few_columns(B, n):
+    """Rows of more than 4096 products over few output columns (one or two
+    8192-column ranges, a range ending past n): dense-panel and bucket
+    segments at the matrix's right edge; small integers, so exact."""
+    A = synth.varnnz_csr(64, 3000, 1, 20, 41, np.float64, "int", stream=0)
+    dense_rows = synth.uniform_csr(3, 3000, 1500, 41, np.float64, "int", stream=2)
+    A = _replace_rows(A, [0, 31, 63], dense_rows)
+    Bm = synth.varnnz_csr(3000, n, 1, min(n, 12), 41, np.float64, "int", stream=1)
+    check(B, A, Bm, np.float64, exact=True, what=f"split rows, n={n}")
+
+
 def _replace_rows(A, rows, R):
     """A with rows `rows` replaced by the rows of R (same column count)."""
     rows = list(rows)
