@@ -440,15 +440,22 @@ def traffic_from_profile(kernel_src_hash):
     return int(fields["traffic_bytes"])
 
 
+# Sources the plain product's numeric pass is built and launched from (its
+# kernels, their headers, the binning that routes its rows, the launchers);
+# the backward, MCL, permutation, split-row and one-thread-per-row sources
+# take no part in it.
+NUMERIC_SOURCES = ("api.hip", "binning.hip", "row_kernels.hip", "wave_kernels.hip",
+                   "rowops.hpp", "common.hpp", "internal.hpp")
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_21444_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in NUMERIC_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()
 
 
