@@ -259,16 +259,30 @@ __global__ void k_det_absmax(const VT *__restrict__ a, int64_t na, const VT *__r
                              int64_t nw, unsigned long long *mx) {
   unsigned long long ma = 0, mw = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na; t += stride)
-    ma = max(ma, abs_bits(a[t]));
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nw; t += stride)
-    mw = max(mw, abs_bits(w[t]));
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t t = t0; t < na; t += stride) ma = max(ma, abs_bits(a[t]));
+  int64_t t = t0;
+  for (; t + 3 * stride < nw; t += 4 * stride) {  // four loads in flight
+    const VT w0 = w[t], w1 = w[t + stride], w2 = w[t + 2 * stride], w3 = w[t + 3 * stride];
+    mw = max(mw, max(max(abs_bits(w0), abs_bits(w1)), max(abs_bits(w2), abs_bits(w3))));
+  }
+  for (; t < nw; t += stride) mw = max(mw, abs_bits(w[t]));
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) {
     ma = max(ma, (unsigned long long)__shfl_xor(ma, off));
     mw = max(mw, (unsigned long long)__shfl_xor(mw, off));
   }
+  __shared__ unsigned long long red[2][8];
   if (lane_id() == 0) {
+    red[0][threadIdx.x / kWave] = ma;
+    red[1][threadIdx.x / kWave] = mw;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one atomic per block and word
+    for (int w8 = 1; w8 < (int)blockDim.x / kWave; ++w8) {
+      ma = max(ma, red[0][w8]);
+      mw = max(mw, red[1][w8]);
+    }
     if (ma) atomicMax(&mx[0], ma);
     if (mw) atomicMax(&mx[1], mw);
   }
