@@ -1,7 +1,8 @@
 // Heavy rows shared by many blocks: the symbolic description of a split
 // row, the scatter of its products into column ranges, and the merge of
-// each segment of ranges (paper §3.3: the rows beyond every shared-memory
-// table; here no row is left to a single compute unit).
+// each segment of ranges (paper §4.4: the level of the row-wise product's
+// multi-level accumulator beyond shared memory; here no row is left to a
+// single compute unit).
 //
 // A row of C = sum_k A_k B_k with many products (a power-law hub) used to
 // be one block's work from its first product to its last output, so the
@@ -302,7 +303,6 @@ struct ScatterPlace {
 // product goes to the next entry of its run.
 template <typename VT>
 __global__ __launch_bounds__(kScatterNT) void k_split_scatter(const Problem *__restrict__ pr,
-                                                              const int32_t *__restrict__ rows,
                                                               WsHeader *__restrict__ hdr, int blo,
                                                               int lS, SplitArgs sa) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -655,8 +655,8 @@ static void num_split(const Problem *dpr, const int32_t *rows, WsHeader *hdr, in
   const size_t sl = scatter_lds<VT>();
   const int sg = D.cus * per_cu(sl, (size_t)kSplitMaxRanges * 4 + (size_t)kScatterNT * (8 + sizeof(VT)),
                                 kScatterNT);
-  hipLaunchKernelGGL(k_split_scatter<VT>, dim3(sg), dim3(kScatterNT), sl, st, dpr, rows, hdr, blo,
-                     lS, sa);
+  hipLaunchKernelGGL(k_split_scatter<VT>, dim3(sg), dim3(kScatterNT), sl, st, dpr, hdr, blo, lS,
+                     sa);
   const size_t ml = merge_lds<VT>();
   const int mg = D.cus * per_cu(ml, 256, kAccumNT);
   hipLaunchKernelGGL(k_split_merge<VT>, dim3(mg), dim3(kAccumNT), ml, st, hdr, blo, sa, ccol,
