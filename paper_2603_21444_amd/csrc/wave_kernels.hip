@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_wave(
 // walks, which is where the hash kernel spends its scalar instructions.
 // Rows with more products than the staging area holds, or a bucket with more
 // than 255 products, go to the sort-based fallback kernel.
-constexpr int kBucketMaxJ = 6;  // staged products per lane (capacity 384)
+constexpr int kBucketMaxJ = 4;  // staged products per lane (capacity 256)
 
 template <typename VT>
 struct BucketInsert {
@@ -699,8 +699,9 @@ __global__ __launch_bounds__(256, SPG_WAVE_WAVES) void k_num_bucket(
 }
 
 // Staging capacity and LDS of the bucket kernel for bin b (T = 2 * edge
-// buckets, 1.5 * edge staged products).
-int bucket_cap(int b) { return (8 << b) + (4 << b); }
+// buckets, edge staged products: the rows of a bin never have more
+// products than its edge, whatever thresholds the tuning picks).
+int bucket_cap(int b) { return 8 << b; }
 bool bucket_ok(int b) {
   const int T = bin_slots(b);
   return T >= 128 && T <= 512 && bucket_cap(b) <= kBucketMaxJ * kWave;
