@@ -50,6 +50,7 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
   __shared__ int sstart[kSplitMaxRanges];
   __shared__ int wtot[16];
   __shared__ int total, item, okflag, segbase, itembase, stagebase, nentries;
+  __shared__ unsigned long long prod64;  // the row's products (the range counters are 32-bit)
   const int n = pr->n;
   const int nw = (n + 31) >> 5;
   uint32_t *map = LDSMAP ? reinterpret_cast<uint32_t *>(smem_raw) : gbitmap + (size_t)blockIdx.x * nw;
@@ -69,22 +70,29 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
         pe[c] = 0;
         de[c] = 0;
       }
-    if (tid == 0) total = 0;
+    if (tid == 0) {
+      total = 0;
+      prod64 = 0;
+    }
     if (!LDSMAP) __threadfence();
     __syncthreads();
-    int mine = 0;
+    int mine = 0;  // described rows: products; others: new distinct columns
     auto fmark = each_product([&](int col, float) {
       const uint32_t bit = 1u << (col & 31);
       if (rec) {  // distinct columns come from the popcounts below
         atomicOr(&map[col >> 5], bit);
         atomicAdd(&pe[col >> kSplitLog2W], 1);
+        ++mine;
       } else {
         const uint32_t old = atomicOr(&map[col >> 5], bit);
         mine += (old & bit) ? 0 : 1;
       }
     });
     for_each_product<true, false, 1024, kSplitSymUnroll, float>(pr, i, true, tid, lS, st, fmark);
-    if (mine) atomicAdd(&total, mine);
+    if (mine) {
+      if (rec) atomicAdd(&prod64, (unsigned long long)mine);
+      else atomicAdd(&total, mine);
+    }
     if (!LDSMAP) __threadfence();
     __syncthreads();
     if (!rec) {
@@ -141,7 +149,9 @@ __global__ __launch_bounds__(1024) void k_sym_split(const Problem *__restrict__ 
         E += ae - as;
       }
       nentries = E;
-      int ok = P > 0 && nseg > 0;
+      // a row of more products than the staging area holds (then its
+      // 32-bit range counters may also have wrapped) is not described
+      int ok = prod64 > 0 && prod64 <= (unsigned long long)sa.pcap && nseg > 0;
       long long b = -1;
       int sg = -1, ib = -1;
       if (ok) {
