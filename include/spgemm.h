@@ -177,7 +177,11 @@ int spgemm_symbolic_noalloc(spg_plan plan, int32_t K, const spg_csr *A, const sp
 
 /* Numeric pass: values and canonical column order of C, for the same K
  * operand patterns as the plan's symbolic call (values may differ: the plan
- * is reusable at fixed sparsity).
+ * is reusable at fixed sparsity).  Patterns that differ from the symbolic
+ * call's are the caller's error: a count that no longer matches is flagged
+ * (SPG_ERR_INVALID), but a change that keeps every row's product and
+ * column counts can go unseen; C is then unspecified, and every write still
+ * stays inside C_col_idx and C_vals.
  *   C_col_idx  device [nnz(C)] int32, written.
  *   C_vals     device [nnz(C)] of dtype, written.
  * Accumulation is in dtype (FP32 or FP64). */
