@@ -352,11 +352,15 @@ __global__ __launch_bounds__(Geom<G>::WG, num_waves<G>()) void k_num_rows(const 
 // (tickets in the bucket of the order-preserving home slot, scan,
 // placement), here with T = edge buckets and 1.125 edge staged products so
 // that three rows of the 2^12-column bin fit one CU's LDS (the hash table
-// needs 16 bytes per column, this 11).  Rows without repeated columns rank
-// each product inside its bucket; other rows sort the buckets and give each
-// thread a contiguous range of positions, whose run starts one block scan
-// turns into output ranks.  Overflowing rows go to the fallback kernel.
+// needs 16 bytes per column, this 11).  Rows with few repeated columns
+// rank each product inside its bucket (less the repeats of smaller columns,
+// listed first); other rows sort the buckets and give each thread a
+// contiguous range of positions, whose run starts one block scan turns into
+// output ranks.  Overflowing rows go to the fallback kernel.
 constexpr int kBktJ = 12;  // staged products per thread at most
+// Rows with at most this many repeated products (products less distinct
+// columns) are ranked inside their buckets; rows with more sort them.
+constexpr int kDupList = 32;
 
 template <typename VT>
 struct BucketInsertB {
@@ -430,8 +434,9 @@ __global__ __launch_bounds__(G) void k_num_bucket_blk(
     int32_t *__restrict__ ccol, VT *__restrict__ cval, int32_t *__restrict__ fb_rows) {
   static_assert(G >= 128 && G <= 1024, "block groups only");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int wcount, overflow, bigmax, bigflag;
+  __shared__ int wcount, overflow, bigmax, bigflag, ndl;
   __shared__ int wtot[G / kWave];
+  __shared__ uint32_t dlist[kDupList];
   const int tid = threadIdx.x;
   const int TW = T / 2;
   uint32_t *cnt = reinterpret_cast<uint32_t *>(smem_raw);
@@ -457,6 +462,7 @@ __global__ __launch_bounds__(G) void k_num_bucket_blk(
       overflow = 0;
       bigmax = 0;
       bigflag = 0;
+      ndl = 0;
     }
     __syncthreads();
     BucketInsertB<VT> ins{cnt, ikey, ival, &wcount, mul, cap, false, &bigflag};
@@ -527,18 +533,56 @@ __global__ __launch_bounds__(G) void k_num_bucket_blk(
       }
       __syncthreads();
       const bool big = bigmax > kBigBucket;
-      if (P == nnz && !big) {
-        // no repeated column: bucket start + smaller columns in the bucket
+      const int ndup = P - nnz;  // repeated products, by the symbolic count
+      if (!big && ndup >= 0 && ndup <= kDupList) {
+        // few repeated columns: a product's output rank is its bucket's
+        // start plus the smaller columns in its bucket, less the repeats of
+        // smaller columns, which a first pass lists; the first product of a
+        // column in its bucket sums the column's products and writes them
+        if (ndup > 0) {
+          for (int p = tid; p < P; p += G) {
+            const uint32_t c = ikey[p];
+            for (int q = bkt_start(cnt, mono_slot(c, mul)); q < p; ++q) {
+              if (ikey[q] == c) {
+                const int e = atomicAdd(&ndl, 1);
+                if (e < kDupList) dlist[e] = c;
+                break;
+              }
+            }
+          }
+          __syncthreads();
+        }
+        const int nd = min(ndl, kDupList);
+        bool bad = ndl != ndup;  // a changed pattern
         for (int p = tid; p < P; p += G) {
           const uint32_t c = ikey[p];
           const uint32_t b = mono_slot(c, mul);
           const int s0 = bkt_start(cnt, b);
           const int s1 = b + 1 < (uint32_t)T ? bkt_start(cnt, b + 1) : P;
           int r = s0;
-          for (int q = s0; q < s1; ++q) r += ikey[q] < c ? 1 : 0;
-          cb[r] = (int)c;
-          vb[r] = ival[p];
+          bool first = true;
+          VT sum = ival[p];
+          for (int q = s0; q < s1; ++q) {
+            const uint32_t k = ikey[q];
+            r += k < c ? 1 : 0;
+            if (k == c && q != p) {
+              if (q < p) first = false;
+              else sum += ival[q];
+            }
+          }
+          if (first) {
+            for (int e = 0; e < nd; ++e) r -= dlist[e] < c ? 1 : 0;
+            if (r < nnz) {
+              cb[r] = (int)c;
+              vb[r] = sum;
+            } else {
+              bad = true;
+            }
+          } else if (ndup == 0) {
+            bad = true;
+          }
         }
+        if (bad) atomicOr(&hdr->status, kStatInvalid);
         __syncthreads();
         continue;
       }
