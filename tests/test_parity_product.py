@@ -176,22 +176,22 @@ def test_split_rows_few_columns(B, n):
 
 
 
-def _planted_repeats(dtype, kind, seed):
-    """Rows of 257..4096 products (the block bucket bins) over 2^22 columns,
-    so chance repeats are rare, plus planted ones: B rows 0..47 all hold
-    column c1 and rows 0..23 also column c2, and A row i takes the first
-    d_i of those rows (d_i = 0..47) among its entries.  Rows then repeat
-    0, a few, up to 32 or more than 32 products, with columns repeated two
-    to 48 times in the middle of the row's column range."""
+def _planted_repeats(dtype, kind, seed, planted=48, entries=(20, 200)):
+    """Rows over 2^22 columns, so chance repeats are rare, plus planted
+    ones: B rows 0..planted-1 all hold column c1 and the first half of them
+    also column c2, and A row i takes the first d_i of those rows
+    (d_i = i mod planted) among its entries, next to `entries` random ones.
+    Rows then repeat 0, a few, or many products, with columns repeated two
+    to `planted` times in the middle of the row's column range."""
     k, n, m = 4000, 1 << 22, 480
     c1, c2 = n // 2 + 7, n // 3
     rng = synth.rng_for(seed, 3)
     brows = []
     for r in range(k):
         c = rng.choice(n, size=int(rng.integers(8, 25)), replace=False)
-        if r < 48:
+        if r < planted:
             c = np.append(c, c1)
-        if r < 24:
+        if r < planted // 2:
             c = np.append(c, c2)
         brows.append(np.unique(c))
     bp = np.zeros(k + 1, dtype=np.int64)
@@ -200,8 +200,9 @@ def _planted_repeats(dtype, kind, seed):
     Bm = synth.HostCSR((k, n), bp, bc, synth.draw_values(rng, bc.size, kind, dtype))
     arows = []
     for i in range(m):
-        d = i % 48
-        extra = rng.choice(np.arange(48, k), size=int(rng.integers(20, 200)), replace=False)
+        d = i % planted
+        extra = rng.choice(np.arange(planted, k), size=int(rng.integers(*entries)),
+                           replace=False)
         arows.append(np.unique(np.concatenate([np.arange(d), extra])))
     ap = np.zeros(m + 1, dtype=np.int64)
     np.cumsum([len(c) for c in arows], out=ap[1:])
@@ -217,6 +218,15 @@ def test_block_rows_with_few_repeated_columns(B, dtype, kind):
     sort (more than 32)."""
     A, Bm = _planted_repeats(dtype, kind, 43)
     check(B, A, Bm, dtype, exact=(kind == "int"), what="planted repeats")
+
+
+@pytest.mark.parametrize("dtype,kind", [(np.float64, "int"), (np.float32, "normal")])
+def test_wave_rows_with_few_repeated_columns(B, dtype, kind):
+    """Rows of about 30..420 products (the one-row-per-wave bins and their
+    neighbours) with 0..21 repeated products: in-bucket ranks without
+    repeats, bucket sort and runs with them."""
+    A, Bm = _planted_repeats(dtype, kind, 47, planted=16, entries=(2, 10))
+    check(B, A, Bm, dtype, exact=(kind == "int"), what="planted repeats, short rows")
 
 def _replace_rows(A, rows, R):
     """A with rows `rows` replaced by the rows of R (same column count)."""
