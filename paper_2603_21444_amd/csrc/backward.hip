@@ -6,8 +6,9 @@
 // (A, B) -> A B restricted to the given patterns.
 //
 // One pass over the forward product set.  Per row i of C the W values go
-// into an LDS hash keyed by column (rows beyond the LDS tables use a dense
-// row in the heavy-slot scratch instead).  Every product (p, q) looks up
+// into an LDS hash keyed by column (FP32: column and value in one 64-bit
+// slot; rows beyond the LDS tables use a dense row in the heavy-slot
+// scratch instead).  Every product (p, q) looks up
 // w = W_i,col(q); dA_p collects w * b_q in an LDS accumulator of its A
 // entry, and a_p * w is added to dB_q with a device-scope float atomic, so
 // the summation order of a dB entry is not fixed.
@@ -70,6 +71,11 @@ __device__ __forceinline__ void det_add(const DetAcc &d, int S, int64_t q, doubl
   if (hi + carry) atomicAdd(reinterpret_cast<unsigned long long *>(&d.hi[q]), hi + carry);
 }
 
+#ifndef SPG_BWD_UNROLL
+#define SPG_BWD_UNROLL 2
+#endif
+constexpr int kBwdUnroll = SPG_BWD_UNROLL;
+
 template <typename VT>
 __global__ void k_fill_zero(VT *p, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -104,16 +110,43 @@ __device__ __forceinline__ void for_each_product_e(const Part &P, int i, int l, 
     }
     const int nE = min(G, nA - c0);
     group_sync<BLOCK>();
-    for (int ee = sg; ee < nE; ee += ES) {
-      const int len = sl[ee];
-      VT part = VT(0);
-      for (int q = q0; q < len; q += S) {
-        const int idx = sb[ee] + q;
-        part += f(bcol[idx], bval[idx], idx, ee);
+    // kBwdUnroll entries at a time: the loads of their first positions are
+    // in flight together before any product is looked up
+    for (int e0 = sg; e0 < nE; e0 += ES * kBwdUnroll) {
+      int len[kBwdUnroll], b0[kBwdUnroll], col[kBwdUnroll];
+      VT part[kBwdUnroll], bv[kBwdUnroll];
+#pragma unroll
+      for (int u = 0; u < kBwdUnroll; ++u) {
+        const int ee = e0 + u * ES;
+        len[u] = ee < nE ? sl[ee] : 0;
+        b0[u] = ee < nE ? sb[ee] : 0;
+        part[u] = VT(0);
       }
-      // the S lanes of entry ee hold its partial sums: reduce, one store
-      for (int off = S / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, S);
-      if (q0 == 0) sd[ee] = part;
+#pragma unroll
+      for (int u = 0; u < kBwdUnroll; ++u) {
+        col[u] = 0;
+        bv[u] = VT(0);
+        if (q0 < len[u]) {
+          col[u] = bcol[b0[u] + q0];
+          bv[u] = bval[b0[u] + q0];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBwdUnroll; ++u) {
+        const int ee = e0 + u * ES;
+        if (q0 < len[u]) part[u] += f(col[u], bv[u], b0[u] + q0, ee);
+        for (int q = q0 + S; q < len[u]; q += S) {
+          const int idx = b0[u] + q;
+          part[u] += f(bcol[idx], bval[idx], idx, ee);
+        }
+      }
+      // the S lanes of an entry hold its partial sums: reduce, one store
+#pragma unroll
+      for (int u = 0; u < kBwdUnroll; ++u) {
+        for (int off = S / 2; off > 0; off >>= 1) part[u] += __shfl_xor(part[u], off, S);
+        const int ee = e0 + u * ES;
+        if (q0 == 0 && ee < nE) sd[ee] = part[u];
+      }
     }
     group_sync<BLOCK>();
     done(as + c0, nE);
@@ -135,16 +168,21 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
     const int32_t *__restrict__ ccol, const VT *__restrict__ w, VT *__restrict__ dA,
     VT *__restrict__ dB, DetAcc det) {
   using GM = BGeom<G>;
+  // FP32: column and W value in one 64-bit slot, so a lookup is one LDS
+  // read per probe; FP64: a key array beside the value array
+  constexpr bool PK = sizeof(VT) == 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int T = 1 << log2T;
   const int rslot = threadIdx.x / G, l = threadIdx.x % G;
+  unsigned long long *slot = reinterpret_cast<unsigned long long *>(smem_raw) + (size_t)rslot * T;
   VT *wv = reinterpret_cast<VT *>(smem_raw) + (size_t)rslot * T;
-  VT *sa = reinterpret_cast<VT *>(smem_raw) + (size_t)GM::R * T + rslot * G;
-  VT *sd = sa + (size_t)GM::R * G;
-  int *key = reinterpret_cast<int *>(reinterpret_cast<VT *>(smem_raw) + (size_t)GM::R * (T + 2 * G)) +
+  int *key = reinterpret_cast<int *>(reinterpret_cast<VT *>(smem_raw) + (size_t)GM::R * T) +
              (size_t)rslot * T;
-  int *sb = reinterpret_cast<int *>(reinterpret_cast<VT *>(smem_raw) + (size_t)GM::R * (T + 2 * G)) +
-            (size_t)GM::R * T + rslot * G;
+  unsigned char *rest = smem_raw + (size_t)GM::R * T * (sizeof(VT) + 4);
+  VT *sa = reinterpret_cast<VT *>(rest) + rslot * G;
+  VT *sd = sa + (size_t)GM::R * G;
+  int *sb = reinterpret_cast<int *>(reinterpret_cast<VT *>(rest) + (size_t)2 * GM::R * G) +
+            rslot * G;
   int *sl = sb + (size_t)GM::R * G;
   if (hdr->status) return;
   const int count = hdr->bin_count[bin];
@@ -154,21 +192,35 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
   for (int ri = blockIdx.x * GM::R + rslot; ri < count; ri += gridDim.x * GM::R) {
     int i = rows[start + ri];
     if (G >= kWave) i = __builtin_amdgcn_readfirstlane(i);
-    for (int s = l; s < T; s += G) key[s] = kEmpty;
+    for (int s = l; s < T; s += G) {
+      if (PK) slot[s] = kEmptySlot;
+      else key[s] = kEmpty;
+    }
     group_sync<GM::BLOCK>();
     const int rs = crp[i], re = crp[i + 1];
     for (int t = rs + l; t < re; t += G) {
       const int col = ccol[t];
       uint32_t h = scramble_slot((uint32_t)col, log2T);
       int probes = 0;
-      while (atomicCAS(&key[h], kEmpty, col) != kEmpty) {
-        if (++probes > T) {  // row longer than the plan's C row: pattern mismatch
-          atomicOr(&hdr->status, kStatInvalid);
-          break;
+      if constexpr (PK) {
+        const unsigned long long sv = slot_make(col, (float)w[t]);
+        while (atomicCAS(&slot[h], kEmptySlot, sv) != kEmptySlot) {
+          if (++probes > T) {  // row longer than the plan's C row: pattern mismatch
+            atomicOr(&hdr->status, kStatInvalid);
+            break;
+          }
+          h = (h + 1) & (T - 1);
         }
-        h = (h + 1) & (T - 1);
+      } else {
+        while (atomicCAS(&key[h], kEmpty, col) != kEmpty) {
+          if (++probes > T) {  // row longer than the plan's C row: pattern mismatch
+            atomicOr(&hdr->status, kStatInvalid);
+            break;
+          }
+          h = (h + 1) & (T - 1);
+        }
+        if (probes <= T) wv[h] = w[t];
       }
-      if (probes <= T) wv[h] = w[t];
     }
     group_sync<GM::BLOCK>();
     for_each_product_e<GM::BLOCK, G, VT>(
@@ -176,15 +228,28 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
         [&](int col, VT b, int idx, int ee) {
           uint32_t h = scramble_slot((uint32_t)col, log2T);
           int probes = 0;
-          int k2;
-          while ((k2 = key[h]) != col) {
-            if (k2 == kEmpty || ++probes > T) {  // product outside the given pattern
-              atomicOr(&hdr->status, kStatInvalid);
-              return VT(0);
+          VT wij;
+          if constexpr (PK) {
+            unsigned long long sv;
+            while (slot_key(sv = slot[h]) != col) {
+              if (slot_key(sv) == kEmpty || ++probes > T) {  // product outside the pattern
+                atomicOr(&hdr->status, kStatInvalid);
+                return VT(0);
+              }
+              h = (h + 1) & (T - 1);
             }
-            h = (h + 1) & (T - 1);
+            wij = (VT)slot_val(sv);
+          } else {
+            int k2;
+            while ((k2 = key[h]) != col) {
+              if (k2 == kEmpty || ++probes > T) {  // product outside the given pattern
+                atomicOr(&hdr->status, kStatInvalid);
+                return VT(0);
+              }
+              h = (h + 1) & (T - 1);
+            }
+            wij = wv[h];
           }
-          const VT wij = wv[h];
           if (dB) {
             if (det.lo) det_add(det, E, idx, sa[ee] * wij);
             else global_add(&dB[idx], sa[ee] * wij);
