@@ -223,42 +223,115 @@ __global__ __launch_bounds__(BGeom<G>::WG) void k_bwd_rows(
       }
     }
     group_sync<GM::BLOCK>();
-    for_each_product_e<GM::BLOCK, G, VT>(
-        P, i, l, lS, sb, sl, sa, sd,
-        [&](int col, VT b, int idx, int ee) {
-          uint32_t h = scramble_slot((uint32_t)col, log2T);
-          int probes = 0;
-          VT wij;
-          if constexpr (PK) {
-            unsigned long long sv;
-            while (slot_key(sv = slot[h]) != col) {
-              if (slot_key(sv) == kEmpty || ++probes > T) {  // product outside the pattern
-                atomicOr(&hdr->status, kStatInvalid);
-                return VT(0);
-              }
-              h = (h + 1) & (T - 1);
+    // products: S lanes per A entry, kBwdUnroll entries at a time.  For
+    // each round of positions the B loads of all entries are issued first,
+    // then all first probes of the W lookups, then the dA terms, and the dB
+    // atomics last, so no load waits behind an atomic.
+    const SPG_GLOBAL int32_t *brp = gp(P.brp);
+    const SPG_GLOBAL int32_t *bcol = gp(P.bcol);
+    const SPG_GLOBAL VT *bval = gp(static_cast<const VT *>(P.bval));
+    const int S = 1 << lS, ES = G >> lS, sg = l >> lS, q0 = l & (S - 1);
+    const int as = gp(P.arp)[i], nA = gp(P.arp)[i + 1] - as;
+    bool miss = false;
+    for (int c0 = 0; c0 < nA; c0 += G) {
+      const int e = c0 + l;
+      if (e < nA) {
+        const int r = gp(P.acol)[as + e];
+        const int b0 = brp[r];
+        sb[l] = b0;
+        sl[l] = brp[r + 1] - b0;
+        sa[l] = gp(static_cast<const VT *>(P.aval))[as + e];
+      }
+      const int nE = min(G, nA - c0);
+      group_sync<GM::BLOCK>();
+      for (int e0 = sg; e0 < nE; e0 += ES * kBwdUnroll) {
+        int len[kBwdUnroll], b0[kBwdUnroll];
+        VT av[kBwdUnroll], part[kBwdUnroll];
+        int mlen = 0;
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u) {
+          const int ee = e0 + u * ES;
+          len[u] = ee < nE ? sl[ee] : 0;
+          b0[u] = ee < nE ? sb[ee] : 0;
+          av[u] = ee < nE ? sa[ee] : VT(0);
+          part[u] = VT(0);
+          mlen = max(mlen, len[u]);
+        }
+        for (int q = q0; q < mlen; q += S) {
+          int col[kBwdUnroll];
+          VT bv[kBwdUnroll], wij[kBwdUnroll];
+#pragma unroll
+          for (int u = 0; u < kBwdUnroll; ++u) {
+            col[u] = -1;
+            bv[u] = VT(0);
+            if (q < len[u]) {
+              col[u] = bcol[b0[u] + q];
+              bv[u] = bval[b0[u] + q];
             }
-            wij = (VT)slot_val(sv);
-          } else {
-            int k2;
-            while ((k2 = key[h]) != col) {
-              if (k2 == kEmpty || ++probes > T) {  // product outside the given pattern
-                atomicOr(&hdr->status, kStatInvalid);
-                return VT(0);
+          }
+          // W lookups: first probes of all entries, then the rare longer
+          // probe paths (bounded by T; a column missing from the row is a
+          // pattern mismatch)
+          uint32_t h[kBwdUnroll];
+          unsigned long long sv[kBwdUnroll];
+          int kw[kBwdUnroll];
+#pragma unroll
+          for (int u = 0; u < kBwdUnroll; ++u) {
+            h[u] = scramble_slot((uint32_t)max(col[u], 0), log2T);
+            if (PK) sv[u] = slot[h[u]];
+            else kw[u] = key[h[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < kBwdUnroll; ++u) {
+            wij[u] = VT(0);
+            if (col[u] < 0) continue;
+            int k = PK ? slot_key(sv[u]) : kw[u];
+            for (int pr2 = 0; k != col[u] && k != kEmpty && pr2 < T; ++pr2) {
+              h[u] = (h[u] + 1) & (T - 1);
+              if (PK) {
+                sv[u] = slot[h[u]];
+                k = slot_key(sv[u]);
+              } else {
+                k = key[h[u]];
               }
-              h = (h + 1) & (T - 1);
             }
-            wij = wv[h];
+            if (k != col[u]) {
+              miss = true;
+              col[u] = -1;
+            } else {
+              wij[u] = PK ? (VT)slot_val(sv[u]) : wv[h[u]];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kBwdUnroll; ++u) {
+            part[u] += wij[u] * bv[u];
+            // keeps the dA terms (and their wait for the B values) ahead of
+            // the dB atomics: a wait placed after the atomics would also
+            // wait for them
+            asm volatile("" : "+v"(part[u]));
           }
           if (dB) {
-            if (det.lo) det_add(det, E, idx, sa[ee] * wij);
-            else global_add(&dB[idx], sa[ee] * wij);
+#pragma unroll
+            for (int u = 0; u < kBwdUnroll; ++u) {
+              if (col[u] < 0) continue;
+              if (det.lo) det_add(det, E, b0[u] + q, av[u] * wij[u]);
+              else global_add(&dB[b0[u] + q], av[u] * wij[u]);
+            }
           }
-          return wij * b;
-        },
-        [&](int p0, int nE) {
-          if (dA && l < nE) dA[p0 + l] = sd[l];
-        });
+        }
+        // the S lanes of an entry hold its partial sums: reduce, one store
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u) {
+          for (int off = S / 2; off > 0; off >>= 1) part[u] += __shfl_xor(part[u], off, S);
+          const int ee = e0 + u * ES;
+          if (q0 == 0 && ee < nE) sd[ee] = part[u];
+        }
+      }
+      group_sync<GM::BLOCK>();
+      if (dA && l < nE) dA[as + c0 + l] = sd[l];
+      group_sync<GM::BLOCK>();
+    }
+    if (miss) atomicOr(&hdr->status, kStatInvalid);  // product outside the given pattern
   }
 }
 
