@@ -221,6 +221,15 @@ def test_block_rows_with_few_repeated_columns(B, dtype, kind):
 
 
 @pytest.mark.parametrize("dtype,kind", [(np.float64, "int"), (np.float32, "normal")])
+def test_split_rows_with_few_repeated_columns(B, dtype, kind):
+    """Rows of about 4150..6200 products over 2^22 columns, split over many
+    blocks: their segments (ranges grouped to at most 4096 products) repeat
+    no product (in-bucket ranks), a few or many (bucket sort and runs)."""
+    A, Bm = _planted_repeats(dtype, kind, 53, planted=48, entries=(260, 330))
+    check(B, A, Bm, dtype, exact=(kind == "int"), what="planted repeats, split rows")
+
+
+@pytest.mark.parametrize("dtype,kind", [(np.float64, "int"), (np.float32, "normal")])
 def test_wave_rows_with_few_repeated_columns(B, dtype, kind):
     """Rows of about 30..420 products (the one-row-per-wave bins and their
     neighbours) with 0..21 repeated products: in-bucket ranks without
