@@ -239,6 +239,50 @@ def test_backward_deterministic_exact_on_integers_with_heavy_rows(B):
     assert np.array_equal(gA.cpu().numpy(), rA)
 
 
+def _unaligned(t, off):
+    """A copy of the 1-D tensor t whose data starts off elements past a
+    16-byte boundary."""
+    import torch
+    buf = torch.zeros(t.numel() + off, dtype=t.dtype, device=t.device)
+    buf[off:] = t
+    return buf[off:]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_backward_deterministic_unaligned_values(B, dtype):
+    """A and W values that start off a 16-byte boundary, with the largest
+    |w| and |a| in the first (unaligned) or the last elements: the scale
+    of the fixed-point sums sees them, and dA, dB are the bits of the
+    aligned run."""
+    A = synth.uniform_csr(3000, 3000, 12, 21, dtype, "normal", stream=0)
+    Bm = synth.uniform_csr(3000, 3000, 12, 21, dtype, "normal", stream=1)
+    plan, dA_, dB_, dC, Cp, W = _backward_case(B, A, Bm, 21, dtype)
+    offs = [1, 3] if dtype == np.float32 else [1]
+    for where in (0, -1):
+        Wd = dC.vals.clone()
+        Wd[where] = 1e3
+        Ad = dA_.vals.clone()
+        Ad[where] = -1e3
+        ref = plan.backward(B.DeviceCSR(dA_.shape, dA_.row_ptr, dA_.col_idx, Ad), dB_,
+                            B.DeviceCSR(dC.shape, dC.row_ptr, dC.col_idx, Wd), deterministic=True)
+        ref = [x.cpu().numpy() for x in ref]
+        for off in offs:
+            got = plan.backward(
+                B.DeviceCSR(dA_.shape, dA_.row_ptr, dA_.col_idx, _unaligned(Ad, off)), dB_,
+                B.DeviceCSR(dC.shape, dC.row_ptr, dC.col_idx, _unaligned(Wd, off)),
+                deterministic=True)
+            assert plan.status() == B.SPG_OK
+            for g, r in zip(got, ref):
+                assert np.array_equal(g.cpu().numpy().view(np.uint8), r.view(np.uint8))
+        A2 = A.with_data(Ad.cpu().numpy())
+        W2 = Wd.cpu().numpy()
+        rA, rB = oracle.backward(_f64(A2), _f64(Bm), Cp, W2.astype(np.float64))
+        sA, sB = _grad_scales(_f64(A2), _f64(Bm), Cp, W2.astype(np.float64))
+        t = tol_for(dtype)
+        assert np.all(np.abs(ref[1] - rB) <= t * sB + 1e-300)
+        assert np.all(np.abs(ref[0] - rA) <= t * sA + 1e-300)
+
+
 def test_backward_deterministic_rejects_non_finite(B):
     import torch
     A = synth.uniform_csr(500, 500, 8, 19, np.float32, "normal", stream=0)
