@@ -285,23 +285,51 @@ struct ScatterCount {
   }
 };
 
+// The staging area of the split rows: FP32 products as one 8-byte word
+// (column in the low half, value bits in the high half: one store in the
+// scatter, one load in the merge); FP64 products as a column array and a
+// value array.
+template <typename VT>
+struct Staging {
+  int32_t *col;
+  VT *val;
+  __device__ __forceinline__ void put(int p, int c, VT v) const {
+    col[p] = c;
+    val[p] = v;
+  }
+  __device__ __forceinline__ void get(int p, int &c, VT &v) const {
+    c = col[p];
+    v = val[p];
+  }
+};
+template <>
+struct Staging<float> {
+  int32_t *col;  // the area's base, 256-byte aligned: read as 8-byte words
+  float *val;    // unused
+  __device__ __forceinline__ void put(int p, int c, float v) const {
+    reinterpret_cast<unsigned long long *>(col)[p] =
+        (unsigned long long)(uint32_t)c | ((unsigned long long)__float_as_uint(v) << 32);
+  }
+  __device__ __forceinline__ void get(int p, int &c, float &v) const {
+    const unsigned long long w = reinterpret_cast<const unsigned long long *>(col)[p];
+    c = (int)(uint32_t)w;
+    v = __uint_as_float((uint32_t)(w >> 32));
+  }
+};
+
 // Pass 2 of an item whose products overflowed the buffer: every product
 // straight to its range's next staging entry.
 template <typename VT>
 struct ScatterPlace {
   int *lc;
-  int32_t *scol;
-  VT *sval;
+  Staging<VT> sg;
   template <int N>
   __device__ __forceinline__ void batch(const int (&col)[N], const VT (&v)[N]) {
 #pragma unroll
     for (int u = 0; u < N; ++u) {
       if (col[u] >= 0) {
         const int p = atomicAdd(&lc[col[u] >> kSplitLog2W], 1);
-        if (p >= 0) {
-          scol[p] = col[u];
-          sval[p] = v[u];
-        }
+        if (p >= 0) sg.put(p, col[u], v[u]);
       }
     }
   }
@@ -328,8 +356,7 @@ __global__ __launch_bounds__(kScatterNT) void k_split_scatter(const Problem *__r
   const int nitems = min(sa.ctl->items, sa.itemcap);
   const int tid = threadIdx.x;
   const int F = sa.F;
-  SPG_GLOBAL int32_t *scol = gpw(sa.scol);
-  SPG_GLOBAL VT *sval = gpw(static_cast<VT *>(sa.sval));
+  const Staging<VT> stg{sa.scol, static_cast<VT *>(sa.sval)};
   Stage<VT> st{sb, sl, sav};
   for (int t = block_next(&sa.ctl->q_scatter, &item); t < nitems;
        t = block_next(&sa.ctl->q_scatter, &item)) {
@@ -367,13 +394,10 @@ __global__ __launch_bounds__(kScatterNT) void k_split_scatter(const Problem *__r
       for (int s = tid; s < nbuf; s += kScatterNT) {
         const int col = bcol[s];
         const int p = atomicAdd(&lc[col >> kSplitLog2W], 1);
-        if (p >= 0) {
-          scol[p] = col;
-          sval[p] = bval[s];
-        }
+        if (p >= 0) stg.put(p, col, bval[s]);
       }
     } else {
-      ScatterPlace<VT> fp{lc, sa.scol, static_cast<VT *>(sa.sval)};
+      ScatterPlace<VT> fp{lc, stg};
       window_products<true, VT>(pr, i, e0, e1, tid, lS, st, fp);
     }
   }
@@ -386,7 +410,7 @@ __global__ __launch_bounds__(kScatterNT) void k_split_scatter(const Problem *__r
 // dense LDS panel of the range's columns, a presence bitmap walked in
 // column order.  Returns the distinct columns written.
 template <typename VT>
-__device__ int merge_dense(const int32_t *__restrict__ scol, const VT *__restrict__ sval, int P,
+__device__ int merge_dense(const Staging<VT> &stg, int P,
                            int c0, int D, VT *panel, uint32_t *bm, int *wtot,
                            SPG_GLOBAL int32_t *cb, SPG_GLOBAL VT *vb, WsHeader *hdr) {
   constexpr int W = 1 << kSplitLog2W;
@@ -402,8 +426,12 @@ __device__ int merge_dense(const int32_t *__restrict__ scol, const VT *__restric
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * kAccumNT;
-      c[u] = p < P ? scol[p] - c0 : -1;
-      v[u] = p < P ? sval[p] : VT(0);
+      c[u] = -1;
+      v[u] = VT(0);
+      if (p < P) {
+        stg.get(p, c[u], v[u]);
+        c[u] -= c0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -445,7 +473,7 @@ __device__ __forceinline__ int seg_bucket(const uint32_t *cnt, uint32_t b) {
 // bucket is large), runs of equal columns summed.  Returns the distinct
 // columns written.
 template <typename VT>
-__device__ int merge_buckets(const int32_t *__restrict__ scol, const VT *__restrict__ sval, int P,
+__device__ int merge_buckets(const Staging<VT> &stg, int P,
                              int c0, int span, int D, uint32_t *cnt, uint32_t *ikey, VT *ival,
                              int *wtot, int *bigmax, SPG_GLOBAL int32_t *cb, SPG_GLOBAL VT *vb,
                              WsHeader *hdr) {
@@ -464,8 +492,13 @@ __device__ int merge_buckets(const int32_t *__restrict__ scol, const VT *__restr
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int p = tid + j * kAccumNT;
-    kc[j] = p < P ? (uint32_t)(scol[p] - c0) : 0u;
-    kv[j] = p < P ? sval[p] : VT(0);
+    kc[j] = 0u;
+    kv[j] = VT(0);
+    if (p < P) {
+      int c;
+      stg.get(p, c, kv[j]);
+      kc[j] = (uint32_t)(c - c0);
+    }
   }
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -601,14 +634,15 @@ __global__ __launch_bounds__(kAccumNT, sizeof(VT) == 4 ? 8 : 4) void k_split_mer
       if (tid == 0 && sg.dcount != 0) atomicOr(&hdr->status, kStatInvalid);
       continue;
     }
-    const int32_t *scol = sa.scol + sg.stage;
-    const VT *sval = static_cast<const VT *>(sa.sval) + sg.stage;
+    // the segment's part of the staging area (FP32: 8-byte words)
+    const Staging<VT> stg{sa.scol + (sizeof(VT) == 4 ? 2 : 1) * (size_t)sg.stage,
+                          static_cast<VT *>(sa.sval) + sg.stage};
     SPG_GLOBAL int32_t *cb = gpw(ccol) + sg.out;
     SPG_GLOBAL VT *vb = gpw(cval) + sg.out;
     const int got = sg.pcount > kSplitSeg
-                        ? merge_dense<VT>(scol, sval, sg.pcount, sg.c0, sg.dcount, panel, bm,
+                        ? merge_dense<VT>(stg, sg.pcount, sg.c0, sg.dcount, panel, bm,
                                           wtot, cb, vb, hdr)
-                        : merge_buckets<VT>(scol, sval, sg.pcount, sg.c0, sg.c1 - sg.c0,
+                        : merge_buckets<VT>(stg, sg.pcount, sg.c0, sg.c1 - sg.c0,
                                             sg.dcount, cnt, ikey, ival, wtot, &bigmax, cb, vb,
                                             hdr);
     if (tid == 0 && got != sg.dcount) atomicOr(&hdr->status, kStatInvalid);
