@@ -288,11 +288,12 @@ struct ScatterCount {
 // The staging area of the split rows: FP32 products as one 8-byte word
 // (column in the low half, value bits in the high half: one store in the
 // scatter, one load in the merge); FP64 products as a column array and a
-// value array.
+// value array.  Global-address-space pointers: global, not flat, memory
+// instructions.
 template <typename VT>
 struct Staging {
-  int32_t *col;
-  VT *val;
+  SPG_GLOBAL int32_t *col;
+  SPG_GLOBAL VT *val;
   __device__ __forceinline__ void put(int p, int c, VT v) const {
     col[p] = c;
     val[p] = v;
@@ -304,14 +305,14 @@ struct Staging {
 };
 template <>
 struct Staging<float> {
-  int32_t *col;  // the area's base, 256-byte aligned: read as 8-byte words
-  float *val;    // unused
+  SPG_GLOBAL int32_t *col;  // the area's base, 256-byte aligned: 8-byte words
+  SPG_GLOBAL float *val;    // unused
   __device__ __forceinline__ void put(int p, int c, float v) const {
-    reinterpret_cast<unsigned long long *>(col)[p] =
+    reinterpret_cast<SPG_GLOBAL unsigned long long *>(col)[p] =
         (unsigned long long)(uint32_t)c | ((unsigned long long)__float_as_uint(v) << 32);
   }
   __device__ __forceinline__ void get(int p, int &c, float &v) const {
-    const unsigned long long w = reinterpret_cast<const unsigned long long *>(col)[p];
+    const unsigned long long w = reinterpret_cast<const SPG_GLOBAL unsigned long long *>(col)[p];
     c = (int)(uint32_t)w;
     v = __uint_as_float((uint32_t)(w >> 32));
   }
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(kScatterNT) void k_split_scatter(const Problem *__r
   const int nitems = min(sa.ctl->items, sa.itemcap);
   const int tid = threadIdx.x;
   const int F = sa.F;
-  const Staging<VT> stg{sa.scol, static_cast<VT *>(sa.sval)};
+  const Staging<VT> stg{gpw(sa.scol), gpw(static_cast<VT *>(sa.sval))};
   Stage<VT> st{sb, sl, sav};
   for (int t = block_next(&sa.ctl->q_scatter, &item); t < nitems;
        t = block_next(&sa.ctl->q_scatter, &item)) {
@@ -635,8 +636,8 @@ __global__ __launch_bounds__(kAccumNT, sizeof(VT) == 4 ? 8 : 4) void k_split_mer
       continue;
     }
     // the segment's part of the staging area (FP32: 8-byte words)
-    const Staging<VT> stg{sa.scol + (sizeof(VT) == 4 ? 2 : 1) * (size_t)sg.stage,
-                          static_cast<VT *>(sa.sval) + sg.stage};
+    const Staging<VT> stg{gpw(sa.scol + (sizeof(VT) == 4 ? 2 : 1) * (size_t)sg.stage),
+                          gpw(static_cast<VT *>(sa.sval) + sg.stage)};
     SPG_GLOBAL int32_t *cb = gpw(ccol) + sg.out;
     SPG_GLOBAL VT *vb = gpw(cval) + sg.out;
     const int got = sg.pcount > kSplitSeg
