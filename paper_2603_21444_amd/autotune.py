@@ -7,9 +7,10 @@ symbolic pass's own lanes per A entry, then over the bin's upper threshold
 (a fraction of the products its LDS tables are sized for: the rows above
 the threshold move to the next bin, whose tables are twice as large, so the
 threshold is also the table load factor of those rows), and keeps the
-fastest; the other bins keep their current setting.  This is the
-architecture-specific tuning of LDS (shared memory) use and team sizes the
-paper's local kernels rely on (§4.4).  Results are cached in a JSON file
+fastest; the other bins keep their current setting.  Rows beyond every LDS
+bin (heavy rows) get their lanes per A entry tuned the same way, in both
+passes.  This is the architecture-specific tuning of LDS (shared memory)
+use and team sizes the paper's local kernels rely on (§4.4).  Results are cached in a JSON file
 keyed by dtype, shape, number of block products and the rounded per-bin row
 histogram, so a capture reuses them without timing.
 """
@@ -40,6 +41,10 @@ CANDIDATES = {
 }
 # candidate lanes per A entry of the symbolic count
 SYM_SUB_CANDIDATES = (4, 8, 16, 32)
+# rows beyond every LDS bin (split over many blocks, or one block each):
+# their bin index and its candidate lanes per A entry, in both passes
+HEAVY_BIN = 12
+HEAVY_SUB_CANDIDATES = (16, 32, 64)
 # candidate upper thresholds of a bin, as fractions of its table capacity
 EDGE_FRACTIONS = (1.0, 0.75, 0.5)
 # the last LDS bin of the product passes keeps its full edge
@@ -125,6 +130,21 @@ def tune(As, Bs, reps: int = 3, cache_path: str | None = None, share: float = 0.
                 if ms < best_ms:
                     best_e, best_ms = e, ms
             t.bin_edge[b] = best_e
+    # heavy rows (more products than the last LDS bin of a pass holds, at
+    # least 4096 each): lanes per A entry of the numeric, then the symbolic pass
+    if HEAVY_BIN < len(counts) and counts[HEAVY_BIN] * 4096 >= share * total:
+        best_ms = _time(As, Bs, t, reps)
+        for field in ("sub", "sym_sub"):
+            arr = getattr(t, field)
+            best = arr[HEAVY_BIN]
+            for s in HEAVY_SUB_CANDIDATES:
+                if s == best:
+                    continue
+                arr[HEAVY_BIN] = s
+                ms = _time(As, Bs, t, reps)
+                if ms < best_ms:
+                    best, best_ms = s, ms
+            arr[HEAVY_BIN] = best
     if use_cache:
         cache[key] = _to_json(t)
         os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -154,10 +174,11 @@ def _from_json(d: dict) -> binding.SpgTuning:
     return t
 
 
-def describe(t: binding.SpgTuning, bins=range(1, 12)) -> dict:
-    """Compact record of a tuning for reports: per LDS bin that differs from
-    the default, lanes per row, lanes per A entry (numeric, symbolic) and the
-    bin's upper threshold (0 = its table capacity)."""
+def describe(t: binding.SpgTuning, bins=range(1, HEAVY_BIN + 1)) -> dict:
+    """Compact record of a tuning for reports: per bin that differs from the
+    default (the LDS bins and the heavy rows' bin), lanes per row, lanes per
+    A entry (numeric, symbolic) and the bin's upper threshold (0 = its table
+    capacity)."""
     d = binding.default_tuning()
     out = {}
     for b in bins:

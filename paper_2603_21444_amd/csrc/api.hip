@@ -200,10 +200,11 @@ spg_tuning default_tuning() {
   for (int b = 0; b < kNB; ++b) {
     t.lanes[b] = lanes[b];
     // lanes per A entry: 16, but 32 for bin 9 (rows of 2049..4096 products,
-    // 512-lane groups), and 4 for the count's one-wave kernel (bin 5), which
-    // gains from more A entries in flight
-    t.sub[b] = b == 9 ? 32 : 16;
-    t.sym_sub[b] = b == 5 ? 4 : b == 9 ? 32 : 16;
+    // 512-lane groups) and for the heavy rows (their B rows are the long
+    // ones of power-law inputs), and 4 for the count's one-wave kernel (bin
+    // 5), which gains from more A entries in flight
+    t.sub[b] = b == 9 || b == kHeavyBin ? 32 : 16;
+    t.sym_sub[b] = b == 5 ? 4 : b == 9 || b == kHeavyBin ? 32 : 16;
   }
   t.heavy_slots = 0;
   t.max_window = kTail;

@@ -17,6 +17,10 @@ def test_every_candidate_is_accepted_by_the_library():
                 t = binding.default_tuning()
                 t.lanes[b], t.sub[b], t.sym_sub[b] = lanes, sub, s
                 p.set_tuning(t)  # raises SpgError when rejected
+    for sub in autotune.HEAVY_SUB_CANDIDATES:
+        t = binding.default_tuning()
+        t.sub[autotune.HEAVY_BIN] = t.sym_sub[autotune.HEAVY_BIN] = sub
+        p.set_tuning(t)
 
 
 def test_every_edge_candidate_is_accepted_and_capacity_enforced():
@@ -50,6 +54,8 @@ def test_candidates_cover_the_default():
     for b, cands in autotune.CANDIDATES.items():
         assert (t.lanes[b], min(t.sub[b], t.lanes[b])) in cands, b
         assert t.sym_sub[b] in autotune.SYM_SUB_CANDIDATES, b
+    assert t.sub[autotune.HEAVY_BIN] in autotune.HEAVY_SUB_CANDIDATES
+    assert t.sym_sub[autotune.HEAVY_BIN] in autotune.HEAVY_SUB_CANDIDATES
 
 
 def test_json_round_trip():
@@ -126,9 +132,13 @@ def test_every_candidate_gives_the_oracle_product(dtype):
         settings.append((f"candidate {i}", t))
     for sub, ssub in ((1, 64), (64, 1)):
         t = binding.default_tuning()
-        for b in range(1, 12):
+        for b in range(1, autotune.HEAVY_BIN + 1):  # the heavy rows' too
             t.sub[b], t.sym_sub[b] = sub, ssub
         settings.append((f"sub {sub} sym_sub {ssub}", t))
+    for sub in autotune.HEAVY_SUB_CANDIDATES:
+        t = binding.default_tuning()
+        t.sub[autotune.HEAVY_BIN] = t.sym_sub[autotune.HEAVY_BIN] = sub
+        settings.append((f"heavy rows: sub {sub}", t))
     for f in autotune.EDGE_FRACTIONS[1:] + (0.3,):
         t = binding.default_tuning()
         for b in range(1, 12):
